@@ -1,0 +1,529 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, an exact-rational brute force, library routines and invariants.
+CPU only.
+"""
+import math
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_1012_2909_amd import synth
+
+
+def cube64():
+    return synth.make_cube(synth.CUBE_64)
+
+
+# ----------------------------------------------------------------------------
+# camera
+# ----------------------------------------------------------------------------
+def test_axis_camera_maps_pixels_to_voxel_quarters():
+    """View along z over the 64^3 face: pixel (row, col) -> x = (col+1/2)/4,
+    y = (row+1/2)/4, z = -1, direction +z, exactly."""
+    cam = synth.camera_axis_z()
+    for col, row in [(0, 0), (255, 255), (17, 200), (128, 3)]:
+        o, d = oracle.ray(cam, col, row)
+        assert tuple(o) == ((col + 0.5) / 4, (row + 0.5) / 4, -1.0)
+        assert tuple(d) == (0.0, 0.0, 1.0)
+
+
+def test_perspective_basis_invariants():
+    cam = synth.orbit_camera((128, 64, 96), seed=11, w=640, h=360)
+    f, r, u = oracle.basis(cam)
+    tgt = np.array(cam.target) - np.array(cam.eye)
+    assert np.allclose(f, tgt / np.linalg.norm(tgt), atol=1e-15)
+    assert abs(np.dot(f, r)) < 1e-15 and abs(np.dot(f, u)) < 1e-15 and abs(np.dot(r, u)) < 1e-15
+    # right-handed: r x u = -f; up lies in the (f, u) plane on u's side
+    assert np.allclose(np.cross(r, u), -f, atol=1e-15)
+    assert np.dot(np.array(cam.up), u) > 0 and abs(np.dot(np.array(cam.up), r)) < 1e-12
+
+
+def test_perspective_ray_angles():
+    """A pixel's ray makes angle atan(|(sx, sy)|) with the view axis, where the
+    frame's vertical half-extent is tan(fovy/2); rays are unit vectors."""
+    W, H = 320, 200
+    cam = synth.orbit_camera((64, 64, 64), seed=3, w=W, h=H, fovy_deg=40.0)
+    f, r, u = oracle.basis(cam)
+    th = math.tan(math.radians(20.0))
+    for col, row in [(0, 0), (W - 1, H - 1), (160, 100), (7, 190)]:
+        o, d = oracle.ray(cam, col, row)
+        assert abs(np.linalg.norm(d) - 1) < 1e-15
+        assert np.array_equal(o, np.array(cam.eye))
+        # image-plane coordinates (distance 1 along f)
+        x = np.dot(d, r) / np.dot(d, f)
+        y = np.dot(d, u) / np.dot(d, f)
+        assert abs(x - ((col + 0.5) / W * 2 - 1) * th * W / H) < 1e-13
+        assert abs(y - (1 - (row + 0.5) / H * 2) * th) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# clip and sample count
+# ----------------------------------------------------------------------------
+def _inside(p, n):
+    return all(0.0 <= p[a] <= n[a] for a in range(3))
+
+
+def test_sample_count_matches_membership_bisection():
+    """n = number of midpoint samples inside the chord, where the chord's
+    entry/exit are found by bisection on box membership (no slab formulas)."""
+    shape = (40, 24, 32)
+    nz, ny, nx = shape
+    cam = synth.orbit_camera(shape, seed=5, w=64, h=48)
+    rng = np.random.default_rng(0)
+    checked = 0
+    for _ in range(60):
+        col, row = int(rng.integers(0, 64)), int(rng.integers(0, 48))
+        hit, t0, t1, n, o, d = oracle.ray_interval(shape, cam, col, row)
+        # locate the chord by dense scan then bisection
+        ts = np.linspace(0, 3 * np.linalg.norm(np.array(cam.eye)), 20001)
+        ins = [_inside(o + t * d, (nx, ny, nz)) for t in ts]
+        if not any(ins):
+            assert not hit or n == 0
+            continue
+        i0 = ins.index(True)
+        i1 = len(ins) - 1 - ins[::-1].index(True)
+
+        def bis(a, b, want_inside_at_b):
+            for _ in range(200):
+                m = 0.5 * (a + b)
+                if _inside(o + m * d, (nx, ny, nz)) == want_inside_at_b:
+                    b = m
+                else:
+                    a = m
+            return b
+
+        te = bis(ts[i0 - 1], ts[i0], True)
+        tx = bis(ts[i1 + 1], ts[i1], True)
+        assert abs(te - t0) < 1e-9 and abs(tx - t1) < 1e-9
+        L = tx - te
+        n_ref = sum(1 for k in range(int(L / 0.5) + 3) if (k + 0.5) * 0.5 < L)
+        assert n == n_ref
+        checked += 1
+    assert checked > 10
+
+
+# ----------------------------------------------------------------------------
+# P1: constant cube closed form
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("v0", [-1.0, 0.5, 2.25])
+@pytest.mark.parametrize("tau", [1.0, 0.99])
+def test_constant_cube_closed_form_axis(v0, tau):
+    vol = np.full((64, 64, 64), v0, np.float32)
+    lut = synth.lut_ramp()
+    a = min(max((v0 + 3) / 13, 0), 1)
+    cam = synth.camera_axis_z(w=32, h=32)
+    res = oracle.render(vol, lut, cam, tau=tau)
+    n = 128
+    if tau < 1:
+        n = min(n, math.ceil(math.log(1 - tau) / math.log(1 - a)))
+    A = 1 - (1 - a) ** n
+    img = res["out"]
+    # table entries are float32(j/255); interpolation reproduces a to ~3e-8
+    assert np.allclose(img[..., 3], A, atol=1e-7, rtol=0)
+    assert np.allclose(img[..., 0], a * A, atol=1e-7, rtol=0)
+    assert (res["taken"] == n).all()
+
+
+def test_constant_cube_closed_form_oblique():
+    """Per perspective ray: A = 1 - (1-a)^n with that ray's sample count."""
+    shape = (48, 40, 56)
+    vol = np.full(shape, 1.0, np.float32)
+    lut = synth.lut_ramp(alpha_scale=1 / 16)
+    cam = synth.orbit_camera(shape, seed=9, w=48, h=36)
+    res = oracle.render(vol, lut, cam, tau=1.0)
+    a = float(oracle.lut_eval(lut, 1.0)[0][3])
+    c = float(oracle.lut_eval(lut, 1.0)[0][0])
+    n = res["taken"]
+    A_ref = 1 - (1 - a) ** n
+    assert np.abs(res["out"][..., 3] - A_ref).max() < 1e-13
+    assert np.abs(res["out"][..., 0] - c * A_ref).max() < 1e-13
+    assert (n > 0).sum() > 200
+
+
+# ----------------------------------------------------------------------------
+# P2: nearest MIP = per-column max
+# ----------------------------------------------------------------------------
+def test_nearest_mip_is_column_max():
+    vol = cube64()
+    cam = synth.camera_axis_z()
+    res = oracle.render(vol, synth.lut_ramp(), cam, mode="mip", filt="nearest")
+    colmax = vol.max(axis=0)                         # (ny, nx)
+    ref = np.repeat(np.repeat(colmax, 4, axis=0), 4, axis=1).astype(np.float64)
+    assert np.array_equal(res["out"], ref)
+    assert (res["flags"] == 0).all()
+
+
+# ----------------------------------------------------------------------------
+# P8: textbook recurrence along columns
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [1.0, 0.99])
+def test_nearest_composite_is_column_recurrence(tau):
+    vol = cube64()
+    lut = synth.lut_ramp()
+    cam = synth.camera_axis_z(w=64, h=64)   # one ray per voxel column (centres)
+    res = oracle.render(vol, lut, cam, filt="nearest", tau=tau)
+    # straight RGBA per voxel by numpy's piecewise-linear interpolation
+    xk = np.linspace(lut.vmin, lut.vmax, lut.table.shape[0])
+    rgba = np.stack([np.interp(vol.astype(np.float64), xk, lut.table[:, c].astype(np.float64))
+                     for c in range(4)], axis=-1)        # (nz, ny, nx, 4)
+    C = np.zeros((64, 64, 3))
+    A = np.zeros((64, 64))
+    done = np.zeros((64, 64), bool)
+    for z in range(64):
+        for _rep in range(2):       # step 1/2: each voxel is sampled twice
+            a = rgba[z, :, :, 3]
+            live = ~done
+            C[live] += ((1 - A) * a)[live][:, None] * rgba[z, :, :, :3][live]
+            A[live] += ((1 - A) * a)[live]
+            if tau < 1:
+                done |= A >= tau
+    ref = np.concatenate([C, A[..., None]], axis=-1)
+    assert np.abs(res["out"] - ref).max() < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# P5 / P6: the table
+# ----------------------------------------------------------------------------
+def test_ramp_table_identity():
+    lut = synth.lut_ramp()
+    for s in np.linspace(-5, 12, 301):
+        rgba = oracle.lut_eval(lut, s)[0]
+        x = min(max((s + 3) / 13, 0), 1)
+        assert np.abs(rgba - x).max() < 6e-8        # entries are float32(j/255)
+
+
+def test_table_matches_numpy_interp():
+    lut = synth.lut_random(4)
+    xk = np.linspace(lut.vmin, lut.vmax, 256)
+    for s in np.random.default_rng(1).uniform(-4, 11, 200):
+        rgba = oracle.lut_eval(lut, s)[0]
+        ref = [np.interp(s, xk, lut.table[:, c].astype(np.float64)) for c in range(4)]
+        assert np.abs(rgba - ref).max() < 1e-14
+
+
+def test_degenerate_tables():
+    vol = cube64()
+    cam = synth.orbit_camera(vol.shape, seed=2, w=40, h=30)
+    t0 = synth.lut_ramp().table.copy()
+    t0[:, 3] = 0
+    z = oracle.render(vol, synth.Lut(t0, -3, 10), cam)
+    assert np.array_equal(z["out"], np.zeros_like(z["out"]))
+    t1 = synth.lut_random(7).table.copy()
+    t1[:, 3] = 1
+    lut1 = synth.Lut(t1, -3, 10)
+    one = oracle.render(vol, lut1, cam)
+    hitm = one["taken"] > 0
+    assert (one["taken"][hitm] == 1).all()           # alpha 1 stops at the first sample
+    # colour = table colour at the first sample's trilinear value
+    rows, cols = np.nonzero(hitm)
+    for (r_, c_) in list(zip(rows, cols))[:50]:
+        hit, t0_, t1_, n, o, d = oracle.ray_interval(vol.shape, cam, c_, r_)
+        p = o + (t0_ + 0.25) * d
+        s, _, _ = oracle.trilinear(vol, p)
+        rgba = oracle.lut_eval(lut1, s)[0]
+        assert np.abs(one["out"][r_, c_] - np.r_[rgba[:3], 1.0]).max() < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# trilinear: linear functions are reproduced
+# ----------------------------------------------------------------------------
+def test_trilinear_reproduces_linear_field():
+    nz, ny, nx = 7, 5, 9
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a, b, c, d0 = 0.25, -0.5, 0.125, 2.0
+    vol = (a * (i + 0.5) + b * (j + 0.5) + c * (k + 0.5) + d0).astype(np.float32)
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        p = rng.uniform([0, 0, 0], [nx, ny, nz])
+        q = np.clip(p, 0.5, np.array([nx, ny, nz]) - 0.5)      # clamp-to-edge extension
+        ref = a * q[0] + b * q[1] + c * q[2] + d0
+        v, idx, wt = oracle.trilinear(vol, p)
+        assert abs(v - ref) < 1e-12
+        assert abs(wt.sum() - 1) < 1e-15 and (wt >= 0).all()
+        assert abs(np.dot(wt, vol.reshape(-1)[idx].astype(np.float64)) - v) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# P4: exact-rational brute force on 2^3 and 3^3 volumes
+# ----------------------------------------------------------------------------
+def _exact_case(n, seed):
+    rng = np.random.default_rng(seed)
+    vol = (rng.integers(-24, 80, size=(n, n, n)) / 8.0).astype(np.float32)   # dyadic
+    table = (rng.integers(0, 17, size=(5, 4)) / 16.0).astype(np.float32)
+    lut = synth.Lut(table, -4.0, 12.0)
+    return vol, lut
+
+
+BASES = {
+    # f, r, u exact rational unit vectors with r = f x up (unit), u = r x f
+    "oblique": ((F(1, 3), F(2, 3), F(2, 3)), (F(2, 3), F(1, 3), F(-2, 3)), (F(2, 3), F(-2, 3), F(1, 3))),
+    "axis_x": ((F(1), F(0), F(0)), (F(0), F(0), F(1)), (F(0), F(1), F(0))),
+}
+
+
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("basis", ["oblique", "axis_x"])
+@pytest.mark.parametrize("mode", ["composite", "mip", "mip_nearest"])
+def test_brute_force_tiny(n, basis, mode):
+    vol, lut = _exact_case(n, seed=10 * n + len(basis))
+    f, r, u = BASES[basis]
+    c0 = [F(n, 2)] * 3
+    eye = [c0[a] - 3 * n * f[a] for a in range(3)]
+    W = H = 6
+    half = F(3 * n, 4)
+    # target and up are exact integer multiples of f and u
+    cam = synth.Camera(synth.ORTHO, tuple(float(e) for e in eye),
+                       tuple(float(e + 3 * fa) for e, fa in zip(eye, f)),
+                       tuple(float(3 * x) for x in u), half_w=float(half), half_h=float(half),
+                       full_w=W, full_h=H)
+    # the oracle's basis is the exact one up to FP64 rounding
+    fo, ro, uo = oracle.basis(cam)
+    assert np.abs(fo - np.array([float(x) for x in f])).max() < 1e-15
+    assert np.abs(ro - np.array([float(x) for x in r])).max() < 1e-15
+    assert np.abs(uo - np.array([float(x) for x in u])).max() < 1e-15
+    Vq = brute.to_frac_volume(vol)
+    Lq = brute.to_frac_lut(lut.table)
+    m = "mip" if mode.startswith("mip") else "composite"
+    filt = "nearest" if mode == "mip_nearest" else "trilinear"
+    res = oracle.render(vol, lut, cam, mode=m, filt=filt, tau=0.99)
+    hits = exact = 0
+    for row in range(H):
+        for col in range(W):
+            ref = brute.render_pixel(Vq, Lq, F(-4), F(12), eye, f, r, u, half, half, W, H, col, row,
+                                     mode=m, filt=filt)
+            got = res["out"][row, col]
+            fl = res["flags"][row, col]
+            # a dyadic exit can coincide with a sample (t_k = t1 exactly): FP64
+            # may then keep or drop it, and the oracle lists both outcomes
+            cands = [got] + ([res["lo"][row, col], res["hi"][row, col]] if fl else [])
+            if m == "mip":
+                if ref is None:
+                    assert got == -np.inf
+                    continue
+                hits += 1
+                if filt == "nearest" and fl == 0:
+                    assert got == float(ref)
+                else:
+                    assert min(abs(c - float(ref)) for c in cands) <= 1e-12 * max(1.0, abs(float(ref)))
+            else:
+                ref = np.array([float(x) for x in ref])
+                if ref[3] > 0:
+                    hits += 1
+                assert min(np.abs(c - ref).max() for c in cands) <= 1e-12
+            exact += fl == 0
+    assert hits >= 4 and exact >= 12
+
+
+# ----------------------------------------------------------------------------
+# P3: bricks composited separately equal the single pass (no early stop)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("B", [1, 5, 7, 16, 100])
+@pytest.mark.parametrize("kind", ["persp", "ortho"])
+def test_bricked_equals_single_pass(B, kind):
+    shape = (20, 14, 17)
+    spec = synth.CubeSpec(shape, 6, seed=21)
+    vol = synth.make_cube(spec)
+    lut = synth.lut_ramp(alpha_scale=1 / 8)
+    if kind == "persp":
+        cam = synth.orbit_camera(shape, seed=B, w=40, h=30)
+    else:
+        cam = synth.Camera(synth.ORTHO, (-30.0, 25.0, -20.0), (8.5, 7.0, 10.0), (0.0, -1.0, 0.0),
+                           half_w=16.0, half_h=12.0, full_w=40, full_h=30)
+    one = oracle.render(vol, lut, cam, tau=1.0)["out"]
+    br = oracle.render_bricked(vol, lut, cam, B, tau=1.0)["out"]
+    assert np.abs(one - br).max() <= 1e-12
+    mip1 = oracle.render(vol, lut, cam, mode="mip", tau=1.0)["out"]
+    mipb = oracle.render_bricked(vol, lut, cam, B, mode="mip")["out"]
+    assert np.array_equal(mip1, mipb)
+
+
+def test_brick_keys_increase_along_rays():
+    """The key order is a visibility order: along every ray the bricks visited
+    have strictly increasing keys (perspective and orthographic)."""
+    shape = (40, 32, 48)
+    B = 8
+    for cam in [synth.orbit_camera(shape, seed=s, w=30, h=20) for s in range(4)] + [
+            synth.Camera(synth.ORTHO, (-50.0, 60.0, 70.0), (24.0, 16.0, 20.0), (0.0, -1.0, 0.0),
+                         half_w=40.0, half_h=30.0, full_w=30, full_h=20)]:
+        for row in range(0, 20, 3):
+            for col in range(0, 30, 3):
+                hit, t0, t1, n, o, d = oracle.ray_interval(shape, cam, col, row)
+                if not hit:
+                    continue
+                keys, last = [], None
+                for k in range(n):
+                    p = o + (t0 + (k + 0.5) * 0.5) * d
+                    cell = tuple(min(int(p[a] // B), [48, 32, 40][a] // B - 1) for a in range(3))
+                    if cell != last:
+                        keys.append(oracle.brick_key(cam, B, *cell))
+                        last = cell
+                assert all(b > a for a, b in zip(keys, keys[1:]))
+
+
+# ----------------------------------------------------------------------------
+# candidate intervals
+# ----------------------------------------------------------------------------
+def test_candidate_interval_brackets_primary():
+    vol = cube64()
+    cam = synth.orbit_camera(vol.shape, seed=1, w=96, h=96)
+    res = oracle.render(vol, synth.lut_ramp(), cam, eps_stop=1e-3)
+    o, lo, hi = res["out"], res["lo"], res["hi"]
+    assert (lo <= o + 1e-15).all() and (o <= hi + 1e-15).all()
+    amb = (res["flags"] & oracle.FLAG_STOP) != 0
+    assert amb.any()
+    assert np.array_equal(lo[~amb], o[~amb]) and np.array_equal(hi[~amb], o[~amb])
+
+
+# ----------------------------------------------------------------------------
+# P9: gradients
+# ----------------------------------------------------------------------------
+def test_adjoint_constant_cube_closed_form():
+    """dA/da = n (1-a)^(n-1) on a constant cube along z (a through alpha entries)."""
+    vol = np.full((16, 16, 16), 2.0, np.float32)
+    t = np.zeros((2, 4), np.float32)
+    t[:, 3] = 0.125                      # constant alpha a = 1/8, colour 0
+    lut = synth.Lut(t, -3, 10)
+    cam = synth.camera_axis_z(16, 16, 16, w=4, h=4)
+    g = np.zeros((4, 4, 4))
+    g[..., 3] = 1.0                      # L = sum of A over pixels
+    gl, gv = oracle.backward(vol, lut, cam, g, tau=1.0)
+    n, a = 32, 0.125
+    dA = n * (1 - a) ** (n - 1)
+    # a = (1-w) L[0,3] + w L[1,3]; the two weights sum to one per sample
+    assert abs(gl[:, 3].sum() - 16 * dA) < 1e-12
+    assert np.abs(gv).max() == 0.0       # flat table: no value sensitivity
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.99])
+def test_adjoint_matches_finite_differences(tau):
+    vol = synth.make_cube(synth.CUBE_FD16)
+    lut = synth.lut_random(55, n=256)
+    lut = synth.Lut(lut.table * np.float32(0.5), lut.vmin, lut.vmax)
+    cam = synth.orbit_camera(vol.shape, seed=5, w=32, h=32)
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((32, 32, 4))
+
+    def loss(v, L):
+        out = oracle.render(v, L, cam, tau=tau, threads=8)["out"]
+        return float(np.sum(g * out))
+
+    gl, gv = oracle.backward(vol, lut, cam, g, tau=tau)
+    # table entries: the image is a polynomial in them, FD is exact to O(h^2)
+    h = 1e-6
+    base = lut.table.astype(np.float64)
+    fd_l = np.zeros_like(base)
+    for j in range(base.shape[0]):
+        for c in range(4):
+            tp, tm = base.copy(), base.copy()
+            tp[j, c] += h
+            tm[j, c] -= h
+            # the table is float32 at the interface: perturb in float64 through a float32-exact step
+            lp = synth.Lut(tp.astype(np.float32), lut.vmin, lut.vmax)
+            lm = synth.Lut(tm.astype(np.float32), lut.vmin, lut.vmax)
+            dh = float(lp.table[j, c]) - float(lm.table[j, c])
+            fd_l[j, c] = (loss(vol, lp) - loss(vol, lm)) / dh
+    scale_l = np.abs(gl).max()
+    assert scale_l > 0
+    assert np.abs(fd_l - gl).max() <= 1e-6 * scale_l
+    # voxels: skip entries whose one-sided differences disagree (a table knot,
+    # a clamp or a stop decision lies within h)
+    hv = 2.0 ** -20
+    flat = vol.reshape(-1)
+    l0 = loss(vol, lut)
+    errs, skipped = [], 0
+    for idx in range(flat.size):
+        vp, vm = flat.copy(), flat.copy()
+        vp[idx] += np.float32(hv)
+        vm[idx] -= np.float32(hv)
+        hp = float(vp[idx]) - float(flat[idx])     # the float32-exact steps
+        hm = float(flat[idx]) - float(vm[idx])
+        lp = loss(vp.reshape(vol.shape), lut)
+        lm = loss(vm.reshape(vol.shape), lut)
+        fwd, bwd = (lp - l0) / hp, (l0 - lm) / hm
+        if abs(fwd - bwd) > 1e-4 * max(1.0, abs(fwd)):
+            skipped += 1
+            continue
+        errs.append(abs(0.5 * (fwd + bwd) - gv.reshape(-1)[idx]))
+    scale_v = np.abs(gv).max()
+    assert skipped < 0.01 * flat.size
+    assert max(errs) <= 1e-6 * scale_v
+
+
+# ----------------------------------------------------------------------------
+# exact ties and an eye inside the cube
+# ----------------------------------------------------------------------------
+def test_sample_on_exit_face_is_excluded():
+    """Step 2 along z through 5 planes: samples at z = 1, 3, 5; the one on the
+    exit face (t_k = t1 exactly) is not taken."""
+    vol = synth.make_cube(synth.CubeSpec((5, 4, 4), 1, seed=3))
+    cam = synth.camera_axis_z(4, 4, 5, w=4, h=4)
+    res = oracle.render(vol, synth.lut_ramp(), cam, mode="mip", filt="nearest", step=2.0, tau=1.0)
+    assert (res["taken"] == 2).all()
+    assert np.array_equal(res["out"], vol[[1, 3]].max(axis=0).astype(np.float64))
+
+
+@pytest.mark.parametrize("kind", ["ortho", "persp"])
+def test_eye_inside_cube_starts_at_eye(kind):
+    vol = np.full((64, 64, 64), 0.5, np.float32)
+    if kind == "ortho":
+        cam = synth.Camera(synth.ORTHO, (32.0, 32.0, 10.0), (32.0, 32.0, 11.0), (0.0, -1.0, 0.0),
+                           half_w=8.0, half_h=8.0, full_w=8, full_h=8)
+        res = oracle.render(vol, synth.lut_ramp(), cam, tau=1.0)
+        assert (res["taken"] == 108).all()        # (k + 1/2)/2 < 54
+    else:
+        cam = synth.Camera(synth.PERSPECTIVE, (32.0, 32.0, 32.0), (32.0, 32.0, 40.0), (0.0, -1.0, 0.0),
+                           fovy_deg=60.0, full_w=8, full_h=8)
+        res = oracle.render(vol, synth.lut_ramp(), cam, tau=1.0)
+        for row in range(8):
+            for col in range(8):
+                hit, t0, t1, n, o, d = oracle.ray_interval(vol.shape, cam, col, row)
+                assert t0 == 0.0 and hit
+                # exit distance to the z = 64 face (the nearest exit for this frustum)
+                assert abs(t1 - 32.0 / d[2]) < 1e-12
+                assert res["taken"][row, col] == math.ceil(t1 / 0.5 - 0.5)
+
+
+# ----------------------------------------------------------------------------
+# brick partition: per-brick partials are the column recurrence over the
+# brick's z-range, with the brick's own early stop
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [1.0, 0.99])
+def test_brick_partials_are_column_segments(tau):
+    vol = cube64()
+    lut = synth.lut_ramp(alpha_scale=0.25)
+    B = 16
+    cam = synth.camera_axis_z(w=64, h=64)
+    xk = np.linspace(lut.vmin, lut.vmax, lut.table.shape[0])
+    rgba = np.stack([np.interp(vol.astype(np.float64), xk, lut.table[:, c].astype(np.float64))
+                     for c in range(4)], axis=-1)
+    parts = []
+    for bz in range(4):
+        C = np.zeros((64, 64, 3))
+        A = np.zeros((64, 64))
+        done = np.zeros((64, 64), bool)
+        for z in range(bz * B, bz * B + B):
+            for _rep in range(2):
+                a = rgba[z, :, :, 3]
+                live = ~done
+                C[live] += ((1 - A) * a)[live][:, None] * rgba[z, :, :, :3][live]
+                A[live] += ((1 - A) * a)[live]
+                if tau < 1:
+                    done |= A >= tau
+        parts.append(np.concatenate([C, A[..., None]], axis=-1))
+    for bz in range(4):
+        for (bx, by) in [(0, 0), (3, 1)]:
+            bid = (bz * 4 + by) * 4 + bx
+            got = oracle.render_bricked(vol, lut, cam, B, filt="nearest", tau=tau, only_brick=bid)["out"]
+            sl = np.s_[by * 16:(by + 1) * 16, bx * 16:(bx + 1) * 16]
+            assert np.abs(got[sl] - parts[bz][sl]).max() < 1e-14
+            mask = np.ones((64, 64), bool)
+            mask[sl] = False
+            assert not got[mask].any()
+    full = oracle.render_bricked(vol, lut, cam, B, filt="nearest", tau=tau)["out"]
+    ref = np.zeros((64, 64, 4))
+    for bz in range(4):                       # +z view: keys increase with bz
+        ref = ref + (1 - ref[..., 3:4]) * parts[bz]
+    assert np.abs(full - ref).max() < 1e-14
