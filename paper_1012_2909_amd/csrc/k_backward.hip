@@ -1,0 +1,148 @@
+// k_backward.hip -- K5: adjoint of the composite render with respect to the
+// transfer-function table and the voxels.
+//
+// The forward pass (k_march / k_slab with save_for_backward) stored, per
+// pixel, the number of samples taken m and the transmittance in front of
+// samples 0, 64, 128, ... (segment checkpoints), so no per-sample state is
+// kept.  Here one lane owns one ray and walks its segments from the last to
+// the first: it replays the segment forward from its checkpoint (writing T_k
+// into LDS), then walks it backwards carrying the suffix sums
+//   S (colour behind the sample, as seen from it) and P (transmittance behind):
+//   dL/dc_k = gC T_k a_k,   dL/da_k = T_k [gC.(c_k - S) + gA P],
+//   S <- a_k c_k + (1 - a_k) S,   P <- (1 - a_k) P,
+// then chains through the table's linear interpolation (LDS-privatised table
+// gradient, flushed once per workgroup) and the trilinear weights (FP32
+// atomics into the (nz, ny, nx) gradient, corners clamped to the cube as the
+// clamp-to-edge sampling does).
+#include "vr_internal.h"
+
+namespace vr {
+
+constexpr int kSeg = 64;        // samples per checkpoint segment
+constexpr int kBackThreads = 128;
+
+__global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
+    extern __shared__ float smem[];
+    const MarchArgs &A = B.m;
+    const int n_l = A.lut.n;
+    float4 *lut = (float4 *)smem;                        // n_l entries
+    float *glut = smem + 4 * n_l;                        // n_l * 4 partial gradients
+    float *tbuf = glut + 4 * n_l;                        // kSeg x blockDim transmittances
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n_l; i += blockDim.x) {
+        lut[i] = A.lut.rgba[i];
+        glut[4 * i] = glut[4 * i + 1] = glut[4 * i + 2] = glut[4 * i + 3] = 0.0f;
+    }
+    __syncthreads();
+
+    const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
+    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + tid;
+    const VolDev &V = A.vol;
+    int32_t m = 0;
+    if (pix < npix) m = A.taken[pix];
+    if (m > 0) {
+        const int px = (int)(pix % A.cam.tile_w), py = (int)(pix / A.cam.tile_w);
+        Ray r{};
+        make_ray(A.cam, V, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
+        int64_t Q0[3], D[3];
+        fix_start(r, A.step, 0, 0.5, Q0, D);
+        const float4 g = B.gout[pix];
+        float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, P = 1.0f;
+        const int nx = V.nx, ny = V.ny, nz = V.nz;
+        const bool use_log = A.trans == 1 || (A.trans == 2 && r.n > 1024);
+        for (int seg = (m - 1) / kSeg; seg >= 0; --seg) {
+            const int k0 = seg * kSeg, k1 = min(k0 + kSeg, m);
+            // forward replay of the segment from its checkpoint
+            float T = A.ckpt[(int64_t)seg * npix + pix];
+            LogTrans lt;
+            if (use_log) lt.L = T > 0.0f ? __builtin_amdgcn_logf(T) : -INFINITY;
+            int64_t q0 = Q0[0] + (int64_t)k0 * D[0], q1 = Q0[1] + (int64_t)k0 * D[1], q2 = Q0[2] + (int64_t)k0 * D[2];
+            for (int k = k0; k < k1; ++k) {
+                tbuf[(k - k0) * blockDim.x + tid] = T;
+                const float s = gsample<float, VR_TRILINEAR>(V, fix_int(q0), fix_int(q1), fix_int(q2), fix_frac(q0),
+                                                             fix_frac(q1), fix_frac(q2));
+                const float a = lut_eval(lut, n_l, A.lut.vmin, A.lut.scale, s).w;
+                T = use_log ? lt.step(a) : T - T * a;
+                q0 += D[0]; q1 += D[1]; q2 += D[2];
+            }
+            // reverse sweep
+            for (int k = k1 - 1; k >= k0; --k) {
+                q0 -= D[0]; q1 -= D[1]; q2 -= D[2];
+                const int ix = fix_int(q0), iy = fix_int(q1), iz = fix_int(q2);
+                const float fx = fix_frac(q0), fy = fix_frac(q1), fz = fix_frac(q2);
+                const float s = gsample<float, VR_TRILINEAR>(V, ix, iy, iz, fx, fy, fz);
+                // table entry and slope
+                float x = (s - A.lut.vmin) * A.lut.scale;
+                const bool clamped = !(x > 0.0f && x < (float)(n_l - 1));
+                x = fminf(fmaxf(x, 0.0f), (float)(n_l - 1));
+                const int j = min((int)x, n_l - 2);
+                const float w = x - (float)j;
+                const float4 La = lut[j], Lb = lut[j + 1];
+                const float c0 = fmaf(w, Lb.x - La.x, La.x), c1 = fmaf(w, Lb.y - La.y, La.y);
+                const float c2 = fmaf(w, Lb.z - La.z, La.z), a = fmaf(w, Lb.w - La.w, La.w);
+                const float Tk = tbuf[(k - k0) * blockDim.x + tid];
+                const float ta = Tk * a;
+                const float d0 = g.x * ta, d1 = g.y * ta, d2 = g.z * ta;
+                const float da = Tk * (g.x * (c0 - S0) + g.y * (c1 - S1) + g.z * (c2 - S2) + g.w * P);
+                // table gradient (LDS-privatised)
+                if (B.grad_lut) {
+                    const float wa = 1.0f - w;
+                    atomicAdd(&glut[4 * j + 0], wa * d0);
+                    atomicAdd(&glut[4 * j + 1], wa * d1);
+                    atomicAdd(&glut[4 * j + 2], wa * d2);
+                    atomicAdd(&glut[4 * j + 3], wa * da);
+                    atomicAdd(&glut[4 * j + 4], w * d0);
+                    atomicAdd(&glut[4 * j + 5], w * d1);
+                    atomicAdd(&glut[4 * j + 6], w * d2);
+                    atomicAdd(&glut[4 * j + 7], w * da);
+                }
+                // value gradient through the table, then the trilinear weights
+                if (B.grad_vol && !clamped) {
+                    const float gs = (d0 * (Lb.x - La.x) + d1 * (Lb.y - La.y) + d2 * (Lb.z - La.z) +
+                                      da * (Lb.w - La.w)) * A.lut.scale;
+                    if (gs != 0.0f) {
+                        const int X0 = min(max(ix, 0), nx - 1), X1 = min(max(ix + 1, 0), nx - 1);
+                        const int Y0 = min(max(iy, 0), ny - 1), Y1 = min(max(iy + 1, 0), ny - 1);
+                        const int Z0 = min(max(iz, 0), nz - 1), Z1 = min(max(iz + 1, 0), nz - 1);
+                        const float wx1 = fx, wx0 = 1.0f - fx, wy1 = fy, wy0 = 1.0f - fy, wz1 = fz, wz0 = 1.0f - fz;
+                        float *gv = B.grad_vol;
+                        const int64_t r00 = ((int64_t)Z0 * ny + Y0) * nx, r10 = ((int64_t)Z0 * ny + Y1) * nx;
+                        const int64_t r01 = ((int64_t)Z1 * ny + Y0) * nx, r11 = ((int64_t)Z1 * ny + Y1) * nx;
+                        unsafeAtomicAdd(gv + r00 + X0, gs * wz0 * wy0 * wx0);
+                        unsafeAtomicAdd(gv + r00 + X1, gs * wz0 * wy0 * wx1);
+                        unsafeAtomicAdd(gv + r10 + X0, gs * wz0 * wy1 * wx0);
+                        unsafeAtomicAdd(gv + r10 + X1, gs * wz0 * wy1 * wx1);
+                        unsafeAtomicAdd(gv + r01 + X0, gs * wz1 * wy0 * wx0);
+                        unsafeAtomicAdd(gv + r01 + X1, gs * wz1 * wy0 * wx1);
+                        unsafeAtomicAdd(gv + r11 + X0, gs * wz1 * wy1 * wx0);
+                        unsafeAtomicAdd(gv + r11 + X1, gs * wz1 * wy1 * wx1);
+                    }
+                }
+                S0 = fmaf(a, c0 - S0, S0);
+                S1 = fmaf(a, c1 - S1, S1);
+                S2 = fmaf(a, c2 - S2, S2);
+                P = P - a * P;
+            }
+        }
+    }
+    __syncthreads();
+    if (B.grad_lut) {
+        for (int i = tid; i < 4 * n_l; i += blockDim.x)
+            if (glut[i] != 0.0f) unsafeAtomicAdd(B.grad_lut + i, glut[i]);
+    }
+}
+
+hipError_t launch_backward(const BackArgs &a, hipStream_t s) {
+    const int64_t npix = (int64_t)a.m.cam.tile_w * a.m.cam.tile_h;
+    const unsigned blocks = (unsigned)((npix + kBackThreads - 1) / kBackThreads);
+    const size_t lds = (size_t)a.m.lut.n * 32 + (size_t)kSeg * kBackThreads * 4;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_backward, dim3(blocks), dim3(kBackThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace vr

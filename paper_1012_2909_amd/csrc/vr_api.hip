@@ -1,0 +1,528 @@
+// vr_api.hip -- the C ABI (include/vr.h): argument and state checks, camera
+// basis, volume layout description, launch shapes, and the host side of the
+// brick, batch and tuning paths.  Every device buffer is the caller's.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vr_ctx.h"
+
+using namespace vr;
+
+static thread_local std::string g_err;
+
+int vr_fail(const vr_ctx *ctx, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) const_cast<vr_ctx *>(ctx)->err = buf;
+    g_err = buf;
+    return code;
+}
+#define fail vr_fail
+
+static int ok(vr_ctx *ctx) {
+    if (ctx) ctx->err.clear();
+    return VR_OK;
+}
+
+static int no_device(vr_ctx *ctx) {
+    return fail(ctx, VR_EDEVICE, "context was created without a device");
+}
+
+int vr_dev_check(vr_ctx *ctx, hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(ctx, VR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return ok(ctx);
+}
+#define dev_check vr_dev_check
+
+void *vr_stage(vr_ctx *ctx, size_t bytes) {
+    if (ctx->stage_pending) {
+        if (hipEventSynchronize(ctx->stage_done) != hipSuccess) return nullptr;
+        ctx->stage_pending = false;
+    }
+    if (bytes > ctx->stage_bytes) {
+        if (ctx->stage) (void)hipHostFree(ctx->stage);
+        ctx->stage = nullptr;
+        ctx->stage_bytes = 0;
+        size_t cap = std::max<size_t>(bytes, 64 * 1024);
+        if (hipHostMalloc(&ctx->stage, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        ctx->stage_bytes = cap;
+    }
+    return ctx->stage;
+}
+
+hipError_t vr_stage_copy(vr_ctx *ctx, void *dst, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dst, ctx->stage, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    if (!ctx->stage_done) {
+        e = hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    e = hipEventRecord(ctx->stage_done, s);
+    if (e == hipSuccess) ctx->stage_pending = true;
+    return e;
+}
+
+static int64_t esize(int32_t dt) { return dt == VR_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// camera basis (host, FP64)
+// ---------------------------------------------------------------------------
+namespace vr {
+bool make_cam(const vr_camera &c, CamDev *o) {
+    double f[3], r[3], u[3];
+    for (int a = 0; a < 3; ++a) f[a] = c.target[a] - c.eye[a];
+    double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(nf > 0) || !std::isfinite(nf)) return false;
+    for (int a = 0; a < 3; ++a) f[a] /= nf;
+    r[0] = f[1] * c.up[2] - f[2] * c.up[1];
+    r[1] = f[2] * c.up[0] - f[0] * c.up[2];
+    r[2] = f[0] * c.up[1] - f[1] * c.up[0];
+    double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(nr > 0) || !std::isfinite(nr)) return false;
+    for (int a = 0; a < 3; ++a) r[a] /= nr;
+    u[0] = r[1] * f[2] - r[2] * f[1];
+    u[1] = r[2] * f[0] - r[0] * f[2];
+    u[2] = r[0] * f[1] - r[1] * f[0];
+    for (int a = 0; a < 3; ++a) {
+        o->eye[a] = c.eye[a];
+        o->f[a] = f[a];
+        o->r[a] = r[a];
+        o->u[a] = u[a];
+    }
+    o->W = c.full_w;
+    o->H = c.full_h;
+    if (c.kind == VR_PERSPECTIVE) {
+        double th = std::tan(c.fovy_deg * M_PI / 360.0);
+        o->a = th * (double)c.full_w / (double)c.full_h;
+        o->b = th;
+    } else {
+        o->a = c.half_w;
+        o->b = c.half_h;
+    }
+    o->kind = c.kind;
+    o->tile_x0 = c.tile_x0;
+    o->tile_y0 = c.tile_y0;
+    o->tile_w = c.tile_w;
+    o->tile_h = c.tile_h;
+    o->pad = 0;
+    return true;
+}
+}  // namespace vr
+
+static int check_camera(vr_ctx *ctx, const vr_camera *c, CamDev *out) {
+    if (!c) return fail(ctx, VR_EINVAL, "camera is NULL");
+    if (c->kind != VR_ORTHO && c->kind != VR_PERSPECTIVE) return fail(ctx, VR_EINVAL, "camera kind %d", c->kind);
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c->eye[a]) || !std::isfinite(c->target[a]) || !std::isfinite(c->up[a]))
+            return fail(ctx, VR_EINVAL, "camera has a non-finite coordinate");
+    if (c->full_w <= 0 || c->full_h <= 0) return fail(ctx, VR_EINVAL, "full frame %dx%d", c->full_w, c->full_h);
+    if (c->tile_w <= 0 || c->tile_h <= 0 || c->tile_x0 < 0 || c->tile_y0 < 0 ||
+        (int64_t)c->tile_x0 + c->tile_w > c->full_w || (int64_t)c->tile_y0 + c->tile_h > c->full_h)
+        return fail(ctx, VR_EINVAL, "viewport (%d,%d,%d,%d) outside the %dx%d frame", c->tile_x0, c->tile_y0,
+                    c->tile_w, c->tile_h, c->full_w, c->full_h);
+    if ((int64_t)c->tile_w * c->tile_h > (int64_t)1 << 31) return fail(ctx, VR_EINVAL, "viewport too large");
+    if (c->kind == VR_PERSPECTIVE && !(c->fovy_deg > 0 && c->fovy_deg < 180))
+        return fail(ctx, VR_EINVAL, "fovy %g not in (0, 180)", c->fovy_deg);
+    if (c->kind == VR_ORTHO && !(c->half_w > 0 && c->half_h > 0 && std::isfinite(c->half_w) && std::isfinite(c->half_h)))
+        return fail(ctx, VR_EINVAL, "orthographic half extents must be > 0");
+    CamDev cd{};
+    if (!make_cam(*c, &cd)) return fail(ctx, VR_EINVAL, "degenerate camera basis (eye == target or up parallel to the view)");
+    if (out) *out = cd;
+    return VR_OK;
+}
+
+int vr_check_params(vr_ctx *ctx, const vr_render_params *p) {
+#define check_params vr_check_params
+    if (!p) return fail(ctx, VR_EINVAL, "params is NULL");
+    if (p->mode != VR_COMPOSITE && p->mode != VR_MIP) return fail(ctx, VR_EINVAL, "mode %d", p->mode);
+    if (p->filter != VR_TRILINEAR && p->filter != VR_NEAREST) return fail(ctx, VR_EINVAL, "filter %d", p->filter);
+    // fixed-point positions resolve 2^-32 voxel: keep the per-sample increment
+    // far above that, and the sample count of any ray within int32
+    if (!(p->step >= 1e-4) || !std::isfinite(p->step) || p->step > 1e6)
+        return fail(ctx, VR_EINVAL, "step %g must be in [1e-4, 1e6]", p->step);
+    if (!(p->ert_alpha > 0)) return fail(ctx, VR_EINVAL, "ert_alpha %g must be > 0", (double)p->ert_alpha);
+    if (p->transmittance < 0 || p->transmittance > 2) return fail(ctx, VR_EINVAL, "transmittance %d", p->transmittance);
+    return VR_OK;
+}
+
+int vr_need_state(vr_ctx *ctx, bool lut_needed) {
+#define need_state vr_need_state
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+    if (ctx->device < 0 && ctx->vol_loaded) return no_device(ctx);
+    if (!ctx->vol_loaded) return fail(ctx, VR_ESTATE, "no volume loaded");
+    if (!ctx->has_camera) return fail(ctx, VR_ESTATE, "no camera set");
+    if (lut_needed && !ctx->has_lut) return fail(ctx, VR_ESTATE, "no transfer function set");
+    return VR_OK;
+}
+
+// Maximum samples of any ray through the cube.
+static int64_t max_samples(const VolDev &v, double step) {
+    double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
+    return (int64_t)std::ceil(diag / step) + 2;
+}
+
+static void select_copy(VolDev &v, const CamDev &c, int32_t forced);
+
+MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const CamDev &cam) {
+#define march_args vr_march_args
+    MarchArgs a{};
+    a.cam = cam;
+    a.vol = ctx->vol;
+    a.lut = ctx->lut;
+    a.step = p->step;
+    a.ert = p->ert_alpha < 1.0f ? 1 : 0;
+    a.thr = 1.0f - p->ert_alpha;
+    if (p->transmittance == VR_TRANS_PRODUCT) a.trans = 0;
+    else if (p->transmittance == VR_TRANS_LOG) a.trans = 1;
+    else a.trans = a.ert ? 2 : 1;
+    a.packet_w = ctx->tune.packet_w;
+    a.packet_h = ctx->tune.packet_h;
+    a.waves = ctx->tune.waves_per_group;
+    a.groups_x = (cam.tile_w + a.packet_w - 1) / a.packet_w;
+    a.unroll = ctx->tune.unroll;
+    select_copy(a.vol, cam, ctx->tune.copy);
+    return a;
+}
+
+// The LDS-staged kernel serves one-brick layouts (the padded cube); the
+// direct-gather kernel walks multi-brick layouts and serves as the fallback.
+static bool use_slab_path(const vr_ctx *ctx) {
+    if (!ctx->vol.single) return false;
+    if (ctx->tune.path == 1) return false;
+    return ctx->tune.waves_per_group == 4;
+}
+
+static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s) {
+    if (use_slab_path(ctx)) {
+        int32_t cap = ctx->tune.lds_kib * 1024 / 4;
+        return launch_slab(a, p->mode, p->filter, a.packet_w, a.packet_h * a.waves, cap, ctx->tune.slab_max, s);
+    }
+    return launch_march(a, p->mode, p->filter, s);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *vr_version(void) { return "vrcube 1.0 (gfx950)"; }
+
+const char *vr_last_error(const vr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int vr_create(vr_ctx **out, int device) {
+    if (!out) return fail(nullptr, VR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (device == -1) {  // host-only context: argument and state checks, no launches
+        vr_ctx *c = new (std::nothrow) vr_ctx();
+        if (!c) return fail(nullptr, VR_ENOMEM, "out of host memory");
+        c->device = -1;
+        *out = c;
+        return VR_OK;
+    }
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(nullptr, VR_EDEVICE, "no HIP device (%s)", hipGetErrorString(e));
+    if (device < 0 || device >= n) return fail(nullptr, VR_EINVAL, "device %d of %d", device, n);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, VR_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    vr_ctx *c = new (std::nothrow) vr_ctx();
+    if (!c) return fail(nullptr, VR_ENOMEM, "out of host memory");
+    c->device = device;
+    *out = c;
+    return VR_OK;
+}
+
+int vr_destroy(vr_ctx *ctx) {
+    if (!ctx) return VR_OK;
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->graph_src) (void)hipGraphDestroy(ctx->graph_src);
+    if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
+    if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    delete ctx;
+    return VR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// volume
+// ---------------------------------------------------------------------------
+
+static bool layout_of(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t B, int32_t orients, VolDev *v,
+                      int64_t *bytes) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return false;
+    if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24)) return false;
+    if (storage != VR_F32 && storage != VR_F16 && storage != VR_BF16) return false;
+    if (orients != 1 && orients != 3) return false;
+    VolDev d{};
+    d.nx = (int32_t)nx; d.ny = (int32_t)ny; d.nz = (int32_t)nz;
+    d.Bx = B > 0 ? (int32_t)std::min<int64_t>(B, nx) : (int32_t)nx;
+    d.By = B > 0 ? (int32_t)std::min<int64_t>(B, ny) : (int32_t)ny;
+    d.Bz = B > 0 ? (int32_t)std::min<int64_t>(B, nz) : (int32_t)nz;
+    d.nbx = (int32_t)((nx + d.Bx - 1) / d.Bx);
+    d.nby = (int32_t)((ny + d.By - 1) / d.By);
+    d.nbz = (int32_t)((nz + d.Bz - 1) / d.Bz);
+    d.Px = (d.Bx + 2 + 7) / 8 * 8; d.Py = d.By + 2; d.Pz = d.Bz + 2;
+    d.brick_elems = (int64_t)d.Px * d.Py * d.Pz;
+    d.dtype = storage;
+    d.single = (d.nbx == 1 && d.nby == 1 && d.nbz == 1) ? 1 : 0;
+    if (orients == 3 && !d.single) return false;       // copies exist for one-brick layouts only
+    d.orients = orients;
+    d.ori = 0;
+    d.sx = 1; d.sy = d.Px; d.sz = d.Px * d.Py;
+    int64_t total = d.brick_elems * d.nbx * d.nby * d.nbz;
+    d.copy_off[0] = 0;
+    for (int c = 1; c < orients; ++c) {
+        int64_t pf, pm, ps;
+        copy_pitches(d, c - 1, pf, pm, ps);
+        d.copy_off[c] = d.copy_off[c - 1] + (pf * pm * ps + 127) / 128 * 128;   // 256-byte aligned copies
+        copy_pitches(d, c, pf, pm, ps);
+        total = d.copy_off[c] + pf * pm * ps;
+    }
+    if (v) *v = d;
+    if (bytes) *bytes = total * esize(storage);
+    return true;
+}
+
+// The copy whose fastest axis runs along the image rows (largest |r_a|): a
+// ray packet spreads mostly along r, so its lanes then share cache lines.
+static void select_copy(VolDev &v, const CamDev &c, int32_t forced) {
+    if (v.orients < 3) return;
+    int o = 0;
+    if (forced >= 0 && forced <= 2) o = forced;
+    else {
+        if (std::fabs(c.r[1]) > std::fabs(c.r[o])) o = 1;
+        if (std::fabs(c.r[2]) > std::fabs(c.r[o])) o = 2;
+    }
+    int64_t pf, pm, ps;
+    copy_pitches(v, o, pf, pm, ps);
+    int64_t st[3];
+    st[o] = 1;
+    st[(o + 1) % 3] = pf;
+    st[(o + 2) % 3] = pf * pm;
+    v.data = (const char *)v.data + v.copy_off[o] * esize(v.dtype);
+    v.sx = (int32_t)st[0];
+    v.sy = (int32_t)st[1];
+    v.sz = (int32_t)st[2];
+    v.ori = o;
+}
+
+int64_t vr_volume_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t brick_edge,
+                        int32_t orientations) {
+    int64_t b = 0;
+    if (!layout_of(nx, ny, nz, storage, brick_edge, orientations, nullptr, &b)) return VR_EINVAL;
+    return b;
+}
+
+int vr_describe_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t brick_edge,
+                       int32_t orientations, void *dst_dev, int64_t dst_bytes) {
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+    VolDev v{};
+    int64_t need = 0;
+    if (!layout_of(nx, ny, nz, storage, brick_edge, orientations, &v, &need))
+        return fail(ctx, VR_EINVAL, "invalid cube %lldx%lldx%lld, storage %d or orientations %d (3 needs one brick)",
+                    (long long)nx, (long long)ny, (long long)nz, storage, orientations);
+    if (v.brick_elems >= ((int64_t)1 << 32))
+        return fail(ctx, VR_EUNSUPPORTED, "a brick of %lld voxels exceeds 2^32; use a smaller brick edge",
+                    (long long)v.brick_elems);
+    for (int c = 1; c < v.orients; ++c) {
+        int64_t pf, pm, ps;
+        copy_pitches(v, c, pf, pm, ps);
+        if (pf * pm * ps >= ((int64_t)1 << 32))
+            return fail(ctx, VR_EUNSUPPORTED, "an orientation copy of %lld voxels exceeds 2^32", (long long)(pf * pm * ps));
+    }
+    if (!dst_dev) return fail(ctx, VR_EINVAL, "destination is NULL");
+    if (dst_bytes < need) return fail(ctx, VR_ENOMEM, "destination holds %lld bytes, layout needs %lld",
+                                      (long long)dst_bytes, (long long)need);
+    v.data = dst_dev;
+    ctx->vol = v;
+    ctx->has_volume = true;
+    ctx->vol_loaded = false;
+    return ok(ctx);
+}
+
+int vr_load_slab(vr_ctx *ctx, const float *src_dev, int64_t z0, int64_t nz_slab, void *stream) {
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+    if (!ctx->has_volume) return fail(ctx, VR_ESTATE, "vr_describe_volume first");
+    if (!src_dev) return fail(ctx, VR_EINVAL, "source is NULL");
+    if (z0 < 0 || nz_slab <= 0 || z0 + nz_slab > ctx->vol.nz)
+        return fail(ctx, VR_EINVAL, "slab [%lld, %lld) outside [0, %d)", (long long)z0, (long long)(z0 + nz_slab),
+                    ctx->vol.nz);
+    if (ctx->device < 0) return no_device(ctx);
+    hipError_t e = launch_transcode(src_dev, ctx->vol, z0, z0 + nz_slab, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_check(ctx, e, "transcode");
+    ctx->vol_loaded = true;
+    return ok(ctx);
+}
+
+int vr_load_volume(vr_ctx *ctx, const float *src_dev, int64_t nx, int64_t ny, int64_t nz, int32_t storage,
+                   int32_t brick_edge, int32_t orientations, void *dst_dev, int64_t dst_bytes, void *stream) {
+    int rc = vr_describe_volume(ctx, nx, ny, nz, storage, brick_edge, orientations, dst_dev, dst_bytes);
+    if (rc != VR_OK) return rc;
+    return vr_load_slab(ctx, src_dev, 0, nz, stream);
+}
+
+// ---------------------------------------------------------------------------
+// table, camera
+// ---------------------------------------------------------------------------
+int vr_set_transfer_function(vr_ctx *ctx, const float *rgba_dev, int32_t n, float vmin, float vmax) {
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+    if (!rgba_dev) return fail(ctx, VR_EINVAL, "table is NULL");
+    if (n < 2 || n > 1024) return fail(ctx, VR_EINVAL, "table size %d not in [2, 1024]", n);
+    if (!(vmax > vmin) || !std::isfinite(vmin) || !std::isfinite(vmax))
+        return fail(ctx, VR_EINVAL, "value range [%g, %g] must have vmax > vmin", (double)vmin, (double)vmax);
+    ctx->lut.rgba = (const float4 *)rgba_dev;
+    ctx->lut.n = n;
+    ctx->lut.vmin = vmin;
+    ctx->lut.scale = (float)((double)(n - 1) / ((double)vmax - (double)vmin));
+    ctx->vmax = vmax;
+    ctx->has_lut = true;
+    return ok(ctx);
+}
+
+int vr_set_camera(vr_ctx *ctx, const vr_camera *cam) {
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+    CamDev cd{};
+    int rc = check_camera(ctx, cam, &cd);
+    if (rc != VR_OK) return rc;
+    ctx->cam = *cam;
+    ctx->camd = cd;
+    ctx->has_camera = true;
+    return ok(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// render
+// ---------------------------------------------------------------------------
+static int64_t ckpt_segs(const vr_ctx *ctx, const vr_render_params *p) {
+    return (max_samples(ctx->vol, p->step) + 63) / 64;
+}
+
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *p) {
+    if (!ctx || !p) return fail(ctx, VR_EINVAL, "NULL argument");
+    if (!ctx->vol_loaded || !ctx->has_camera) return fail(ctx, VR_ESTATE, "volume and camera first");
+    if (check_params(const_cast<vr_ctx *>(ctx), p) != VR_OK) return VR_EINVAL;
+    if (!p->save_for_backward) return 0;
+    int64_t npix = (int64_t)ctx->cam.tile_w * ctx->cam.tile_h;
+    return align256(npix * 4) + ckpt_segs(ctx, p) * npix * 4;
+}
+
+int vr_render(vr_ctx *ctx, const vr_render_params *p, float *out_dev, void *ws, int64_t ws_bytes, void *stream) {
+    int rc = need_state(ctx, p && p->mode == VR_COMPOSITE);
+    if (rc != VR_OK) return rc;
+    if ((rc = check_params(ctx, p)) != VR_OK) return rc;
+    if (!out_dev) return fail(ctx, VR_EINVAL, "output is NULL");
+    MarchArgs a = march_args(ctx, p, ctx->camd);
+    a.out = out_dev;
+    if (p->save_for_backward) {
+        if (p->mode != VR_COMPOSITE) return fail(ctx, VR_EUNSUPPORTED, "save_for_backward needs composite mode");
+        int64_t need = vr_render_workspace_bytes(ctx, p);
+        if (!ws || ws_bytes < need)
+            return fail(ctx, VR_ENOMEM, "workspace %lld bytes, need %lld", (long long)ws_bytes, (long long)need);
+        int64_t npix = (int64_t)ctx->cam.tile_w * ctx->cam.tile_h;
+        a.taken = (int32_t *)ws;
+        a.ckpt = (float *)((char *)ws + align256(npix * 4));
+        a.ckpt_segs = (int32_t)ckpt_segs(ctx, p);
+    }
+    return dev_check(ctx, dispatch_render(ctx, a, p, (hipStream_t)stream), "render");
+}
+
+int vr_render_backward(vr_ctx *ctx, const vr_render_params *p, const float *grad_out, const void *ws,
+                       int64_t ws_bytes, float *grad_lut, float *grad_vol, void *stream) {
+    int rc = need_state(ctx, true);
+    if (rc != VR_OK) return rc;
+    if ((rc = check_params(ctx, p)) != VR_OK) return rc;
+    if (p->mode != VR_COMPOSITE || p->filter != VR_TRILINEAR)
+        return fail(ctx, VR_EUNSUPPORTED, "gradients need composite mode with trilinear sampling");
+    if (!ctx->vol.single || ctx->vol.dtype != VR_F32)
+        return fail(ctx, VR_EUNSUPPORTED, "gradients need a one-brick FP32 layout");
+    if (!grad_out) return fail(ctx, VR_EINVAL, "grad_out is NULL");
+    vr_render_params q = *p;
+    q.save_for_backward = 1;
+    const int64_t need = vr_render_workspace_bytes(ctx, &q);
+    if (!ws || ws_bytes < need)
+        return fail(ctx, VR_ENOMEM, "workspace %lld bytes, need %lld", (long long)ws_bytes, (long long)need);
+    if (!grad_lut && !grad_vol) return ok(ctx);
+    MarchArgs a = march_args(ctx, &q, ctx->camd);
+    const int64_t npix = (int64_t)ctx->cam.tile_w * ctx->cam.tile_h;
+    a.taken = (int32_t *)ws;
+    a.ckpt = (float *)((char *)ws + align256(npix * 4));
+    a.ckpt_segs = (int32_t)ckpt_segs(ctx, &q);
+    BackArgs b{};
+    b.m = a;
+    b.gout = (const float4 *)grad_out;
+    b.grad_lut = grad_lut;
+    b.grad_vol = grad_vol;
+    return dev_check(ctx, launch_backward(b, (hipStream_t)stream), "backward");
+}
+
+int vr_count_samples(vr_ctx *ctx, const vr_render_params *p, int32_t *counts, void *stream) {
+    int rc = need_state(ctx, p && p->mode == VR_COMPOSITE);
+    if (rc != VR_OK) return rc;
+    if ((rc = check_params(ctx, p)) != VR_OK) return rc;
+    if (!counts) return fail(ctx, VR_EINVAL, "counts is NULL");
+    MarchArgs a = march_args(ctx, p, ctx->camd);
+    a.counts = counts;
+    return dev_check(ctx, dispatch_render(ctx, a, p, (hipStream_t)stream), "count");
+}
+
+int64_t vr_touched_bitmap_bytes(const vr_ctx *ctx) {
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+    if (!ctx->has_volume) return fail(ctx, VR_ESTATE, "no volume");
+    int64_t nb = (int64_t)((ctx->vol.nx + 7) / 8) * ((ctx->vol.ny + 7) / 8) * ((ctx->vol.nz + 7) / 8);
+    return ((nb + 31) / 32) * 4;
+}
+
+int vr_mark_touched_blocks(vr_ctx *ctx, const vr_render_params *p, uint32_t *bitmap, int64_t bytes, void *stream) {
+    int rc = need_state(ctx, p && p->mode == VR_COMPOSITE);
+    if (rc != VR_OK) return rc;
+    if ((rc = check_params(ctx, p)) != VR_OK) return rc;
+    if (!bitmap || bytes < vr_touched_bitmap_bytes(ctx)) return fail(ctx, VR_ENOMEM, "bitmap too small");
+    MarchArgs a = march_args(ctx, p, ctx->camd);
+    return dev_check(ctx, launch_touch(a, p->mode, p->filter, bitmap, (hipStream_t)stream), "touch");
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+int vr_get_tuning(const vr_ctx *ctx, vr_tuning *out) {
+    if (!ctx || !out) return fail(ctx, VR_EINVAL, "NULL argument");
+    *out = ctx->tune;
+    return VR_OK;
+}
+
+static bool tuning_valid(const vr_tuning &t) {
+    bool shape = (t.packet_w == 8 && t.packet_h == 8) || (t.packet_w == 16 && t.packet_h == 4) ||
+                 (t.packet_w == 32 && t.packet_h == 2) || (t.packet_w == 64 && t.packet_h == 1) ||
+                 (t.packet_w == 4 && t.packet_h == 16);
+    bool waves = t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4 || t.waves_per_group == 8;
+    bool unroll = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
+    bool pg = t.persistent_groups >= 1 && t.persistent_groups <= 32;
+    bool path = t.path >= 0 && t.path <= 2;
+    bool lds = t.lds_kib >= 8 && t.lds_kib <= 144;  // + 16 KiB table: within the 160 KiB of LDS
+    bool slab = t.slab_max >= 1 && t.slab_max <= 64;
+    // the LDS-staged kernel is compiled for 256-thread workgroups
+    bool slab_shape = t.path != 2 || t.waves_per_group == 4;
+    bool copy = t.copy >= -1 && t.copy <= 2;
+    return shape && waves && unroll && pg && path && lds && slab && slab_shape && copy;
+}
+
+int vr_set_tuning(vr_ctx *ctx, const vr_tuning *t) {
+    if (!ctx || !t) return fail(ctx, VR_EINVAL, "NULL argument");
+    if (!tuning_valid(*t)) return fail(ctx, VR_EINVAL, "invalid launch shape");
+    ctx->tune = *t;
+    return ok(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// vr_ctx.h -- the context object behind vr_ctx* and the helpers the C ABI
+// files share (error reporting, state and argument checks, staging).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "vr_internal.h"
+
+struct vr_ctx {
+    int device = 0;       // -1: host-only context (checks, no launches)
+    std::string err;
+    // volume
+    bool has_volume = false;
+    vr::VolDev vol{};
+    bool vol_loaded = false;
+    // table
+    bool has_lut = false;
+    vr::LutDev lut{};
+    float vmax = 1.0f;
+    // camera
+    bool has_camera = false;
+    vr_camera cam{};
+    vr::CamDev camd{};
+    // launch shape
+    vr_tuning tune{16, 4, 4, 1, 4, 0, 48, 16, -1};
+    // pinned staging for small device tables, and the event of its last copy
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
+    bool stage_pending = false;
+    // batch graph cache
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;
+    std::vector<int64_t> graph_key;
+    void *graph_stream = nullptr;
+};
+
+int vr_fail(const vr_ctx *ctx, int code, const char *fmt, ...);
+int vr_dev_check(vr_ctx *ctx, hipError_t e, const char *what);
+int vr_check_params(vr_ctx *ctx, const vr_render_params *p);
+int vr_need_state(vr_ctx *ctx, bool lut_needed);
+vr::MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const vr::CamDev &cam);
+// Pinned host staging of at least `bytes`; waits for the previous copy out of
+// it first.  NULL on failure.
+void *vr_stage(vr_ctx *ctx, size_t bytes);
+// Copy the first `bytes` of the staging area to dst on stream s and record
+// the copy's completion.
+hipError_t vr_stage_copy(vr_ctx *ctx, void *dst, size_t bytes, hipStream_t s);

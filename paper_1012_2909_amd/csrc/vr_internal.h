@@ -1,0 +1,99 @@
+// vr_internal.h -- host-side launchers implemented by the kernel files and
+// called by the C ABI layer (vr_api.hip).
+#pragma once
+
+#include "vr_common.h"
+
+namespace vr {
+
+struct MarchArgs {
+    CamDev cam;
+    VolDev vol;
+    LutDev lut;
+    double step;
+    float thr;            // stop when T <= thr, thr = 1 - ert_alpha (ERT on)
+    int32_t ert;          // early termination enabled
+    void *out;            // float4 (composite) / float (MIP) per tile pixel, or NULL
+    int32_t *counts;      // samples taken per pixel, or NULL
+    float *ckpt;          // transmittance before samples 0, 64, 128, ... (segment-major), or NULL
+    int32_t *taken;       // samples taken per pixel (for the adjoint), or NULL
+    int32_t ckpt_segs;    // checkpoints per pixel
+    int32_t trans;        // 0 product, 1 log, 2 per-ray choice (log when n > 1024)
+    // launch shape
+    int32_t packet_w, packet_h;   // pixels per 64-lane packet
+    int32_t waves;                // packets per workgroup (stacked vertically)
+    int32_t groups_x;             // workgroups per tile row
+    int32_t unroll;               // samples per inner iteration (direct path, one-brick layouts)
+};
+
+// K0: transcode planes [z0, z1) of a float32 (z1-z0, ny, nx) source block
+// into the brick-major layout at vol.data.
+hipError_t launch_transcode(const float *src, const VolDev &vol, int64_t z0, int64_t z1, hipStream_t s);
+
+// K1/K2: single-pass render of the camera's viewport.
+hipError_t launch_march(const MarchArgs &a, int32_t mode, int32_t filter, hipStream_t s);
+
+// K1/K2 with LDS-staged voxel boxes (single-brick layouts).
+hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t bw, int32_t bh, int32_t cap_floats,
+                       int32_t lmax, hipStream_t s);
+
+// K7: mark touched 8^3 blocks.
+hipError_t launch_touch(const MarchArgs &a, int32_t mode, int32_t filter, uint32_t *bitmap, hipStream_t s);
+
+// K3: per-brick partials.  The table (device) holds one BrickJob per partial.
+struct BrickJob {
+    float *data;          // partial image (w*h*4 or w*h)
+    int32_t x0, y0, w, h; // footprint (tile-local)
+    int32_t bx, by, bz;   // brick cell
+    int32_t tiles_x;      // 16x16 pixel tiles across the footprint
+    int32_t tile_begin;   // first tile index of this job in the flattened launch
+    int32_t pad;
+};
+hipError_t launch_bricks(const MarchArgs &a, int32_t mode, int32_t filter, const BrickJob *jobs_dev,
+                         int32_t n_jobs, int32_t total_tiles, hipStream_t s);
+
+// K4: composite partials (rectangles in visibility order) into the image.
+struct PartRect {
+    const float *data;
+    int32_t x0, y0, w, h;
+};
+hipError_t launch_composite(const PartRect *rects_dev, int32_t n, int32_t mode, float *out,
+                            int32_t tile_w, int32_t tile_h, hipStream_t s);
+
+// K5: adjoint.
+struct BackArgs {
+    MarchArgs m;
+    const float4 *gout;
+    float *grad_lut;      // n*4 or NULL
+    float *grad_vol;      // (nz,ny,nx) or NULL
+};
+hipError_t launch_backward(const BackArgs &a, hipStream_t s);
+
+// K6: persistent batch.
+struct ViewDev {
+    CamDev cam;
+    void *out;
+    int32_t lut_index;
+    int32_t tiles_x;      // packet-group tiles across the view
+    int32_t tile_begin;   // first work item of the view
+    int32_t pad;
+};
+struct BatchArgs {
+    VolDev vol;
+    const ViewDev *views;
+    int32_t n_views;
+    int32_t total_items;
+    const float4 *luts;
+    int32_t lut_n;
+    float vmin, scale;
+    double step;
+    float thr;
+    int32_t ert;
+    int32_t mode, filter;
+    uint32_t *queue;      // work-queue counter (reset by the launcher each call)
+    int32_t packet_w, packet_h, waves;
+};
+hipError_t launch_batch(const BatchArgs &a, int32_t groups, hipStream_t s);
+hipError_t launch_reset_u32(uint32_t *p, int32_t n, hipStream_t s);
+
+}  // namespace vr

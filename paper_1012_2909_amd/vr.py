@@ -1,0 +1,349 @@
+"""Python binding of the HIP ray caster (libvrcube.so, include/vr.h).
+
+Argument marshalling only: every step of rendering runs in the library's HIP
+kernels.  PyTorch provides device memory (every buffer is a torch tensor the
+binding allocates and keeps alive) and the HIP stream (the current torch
+stream).  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvrcube.so")
+
+OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+MODES = {"composite": 0, "mip": 1}
+FILTERS = {"trilinear": 0, "nearest": 1}
+TRANS = {"auto": 0, "product": 1, "log": 2}
+
+
+class Camera(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("up", C.c_double * 3), ("fovy_deg", C.c_double), ("half_w", C.c_double),
+                ("half_h", C.c_double), ("full_w", C.c_int32), ("full_h", C.c_int32),
+                ("tile_x0", C.c_int32), ("tile_y0", C.c_int32), ("tile_w", C.c_int32),
+                ("tile_h", C.c_int32)]
+
+
+class RenderParams(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("filter", C.c_int32), ("step", C.c_double),
+                ("ert_alpha", C.c_float), ("transmittance", C.c_int32),
+                ("save_for_backward", C.c_int32)]
+
+
+class Partial(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("x0", C.c_int32), ("y0", C.c_int32), ("w", C.c_int32),
+                ("h", C.c_int32), ("brick_id", C.c_int32), ("pad", C.c_int32)]
+
+
+class View(C.Structure):
+    _fields_ = [("cam", Camera), ("lut_index", C.c_int32), ("pad", C.c_int32), ("out", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("packet_w", C.c_int32), ("packet_h", C.c_int32), ("waves_per_group", C.c_int32),
+                ("unroll", C.c_int32), ("persistent_groups", C.c_int32), ("path", C.c_int32),
+                ("lds_kib", C.c_int32), ("slab_max", C.c_int32), ("copy", C.c_int32)]
+
+
+# (name, restype, argtypes) of every exported entry point
+P, I32, I64, F32, D = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+SIGNATURES = [
+    ("vr_create", C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    ("vr_destroy", C.c_int, [P]),
+    ("vr_last_error", C.c_char_p, [P]),
+    ("vr_version", C.c_char_p, []),
+    ("vr_volume_bytes", I64, [I64, I64, I64, I32, I32, I32]),
+    ("vr_load_volume", C.c_int, [P, P, I64, I64, I64, I32, I32, I32, P, I64, P]),
+    ("vr_describe_volume", C.c_int, [P, I64, I64, I64, I32, I32, I32, P, I64]),
+    ("vr_load_slab", C.c_int, [P, P, I64, I64, P]),
+    ("vr_set_transfer_function", C.c_int, [P, P, I32, F32, F32]),
+    ("vr_set_camera", C.c_int, [P, C.POINTER(Camera)]),
+    ("vr_render_workspace_bytes", I64, [P, C.POINTER(RenderParams)]),
+    ("vr_render", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, P]),
+    ("vr_count_samples", C.c_int, [P, C.POINTER(RenderParams), P, P]),
+    ("vr_touched_bitmap_bytes", I64, [P]),
+    ("vr_mark_touched_blocks", C.c_int, [P, C.POINTER(RenderParams), P, I64, P]),
+    ("vr_bricks_pool_bytes", I64, [P, C.POINTER(RenderParams)]),
+    ("vr_render_bricks", C.c_int, [P, C.POINTER(RenderParams), C.POINTER(Partial), I32,
+                                   C.POINTER(I32), P, I64, P]),
+    ("vr_brick_order", C.c_int, [P, C.POINTER(Partial), I32, C.POINTER(I32)]),
+    ("vr_composite_workspace_bytes", I64, [I32]),
+    ("vr_composite_bricks", C.c_int, [P, C.POINTER(RenderParams), C.POINTER(Partial),
+                                      C.POINTER(I32), I32, P, P, I64, P]),
+    ("vr_render_backward", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, P, P, P]),
+    ("vr_batch_workspace_bytes", I64, [P, C.POINTER(View), I32]),
+    ("vr_render_batch", C.c_int, [P, C.POINTER(RenderParams), C.POINTER(View), I32, P, I32, I32,
+                                  F32, F32, P, I64, I32, P]),
+    ("vr_get_tuning", C.c_int, [P, C.POINTER(Tuning)]),
+    ("vr_set_tuning", C.c_int, [P, C.POINTER(Tuning)]),
+    ("vr_autotune", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, C.c_char_p, P]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class VRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vr error {code}: {msg}")
+        self.code = code
+
+
+def check(rc, ctx=None):
+    if rc < 0:
+        msg = lib().vr_last_error(ctx)
+        raise VRError(int(rc), msg.decode() if msg else "")
+    return rc
+
+
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.kind = int(cam.kind)
+    for i in range(3):
+        c.eye[i], c.target[i], c.up[i] = cam.eye[i], cam.target[i], cam.up[i]
+    c.fovy_deg, c.half_w, c.half_h = cam.fovy_deg, cam.half_w, cam.half_h
+    c.full_w, c.full_h = int(cam.full_w), int(cam.full_h)
+    c.tile_x0, c.tile_y0, c.tile_w, c.tile_h = (int(v) for v in cam.tile)
+    return c
+
+
+def params_struct(mode="composite", filt="trilinear", step=0.5, ert=0.99, trans="auto",
+                  save=False) -> RenderParams:
+    p = RenderParams()
+    p.mode = MODES[mode]
+    p.filter = FILTERS[filt]
+    p.step = float(step)
+    p.ert_alpha = float(ert)
+    p.transmittance = TRANS[trans]
+    p.save_for_backward = 1 if save else 0
+    return p
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Renderer:
+    """One rendering context on one GPU.  Holds references to every tensor the
+    library borrows (volume storage, transfer table)."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        check(lib().vr_create(C.byref(h), device))
+        self.ctx = h
+        self.storage = None
+        self.lut = None
+        self.shape = None
+        self.cam = None
+
+    def close(self):
+        if self.ctx:
+            lib().vr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        return check(rc, self.ctx)
+
+    # ---- volume --------------------------------------------------------
+    @staticmethod
+    def default_orientations(shape, brick):
+        return 3 if brick <= 0 or all(brick >= d for d in shape) else 1
+
+    def load_volume(self, vol, storage="f32", brick=0, orientations=None):
+        """vol: float32 (nz, ny, nx) cuda tensor (or numpy array, uploaded).
+        orientations: 3 keeps x-, y- and z-fastest copies (one-brick layouts;
+        the default there), 1 the x-fastest copy only."""
+        if not torch.is_tensor(vol):
+            vol = torch.from_numpy(vol)
+        vol = vol.to(self.device, torch.float32).contiguous()
+        nz, ny, nx = vol.shape
+        if orientations is None:
+            orientations = self.default_orientations(vol.shape, int(brick))
+        nbytes = int(lib().vr_volume_bytes(nx, ny, nz, DTYPES[storage], int(brick), int(orientations)))
+        if nbytes < 0:
+            raise VRError(nbytes, "invalid volume size")
+        self.storage = None
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._check(lib().vr_load_volume(self.ctx, _ptr(vol), nx, ny, nz, DTYPES[storage], int(brick),
+                                         int(orientations), _ptr(self.storage), nbytes, _stream()))
+        self.orientations = int(orientations)
+        self.shape = (nz, ny, nx)
+        self.brick = int(brick)
+        self.storage_dtype = storage
+        return self.storage
+
+    def describe_volume(self, shape, storage="f32", brick=0, orientations=None):
+        nz, ny, nx = shape
+        if orientations is None:
+            orientations = self.default_orientations(shape, int(brick))
+        nbytes = int(lib().vr_volume_bytes(nx, ny, nz, DTYPES[storage], int(brick), int(orientations)))
+        if nbytes < 0:
+            raise VRError(nbytes, "invalid volume size")
+        self.storage = None
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._check(lib().vr_describe_volume(self.ctx, nx, ny, nz, DTYPES[storage], int(brick),
+                                             int(orientations), _ptr(self.storage), nbytes))
+        self.orientations = int(orientations)
+        self.shape = tuple(shape)
+        self.brick = int(brick)
+        self.storage_dtype = storage
+
+    def load_slab(self, slab, z0):
+        slab = slab.to(self.device, torch.float32).contiguous()
+        self._check(lib().vr_load_slab(self.ctx, _ptr(slab), int(z0), int(slab.shape[0]), _stream()))
+
+    # ---- table / camera ------------------------------------------------
+    def set_transfer_function(self, table, vmin, vmax):
+        if not torch.is_tensor(table):
+            table = torch.from_numpy(table)
+        table = table.to(self.device, torch.float32).contiguous()
+        self._check(lib().vr_set_transfer_function(self.ctx, _ptr(table), int(table.shape[0]),
+                                                   float(vmin), float(vmax)))
+        self.lut = table
+        self.lut_range = (float(vmin), float(vmax))
+
+    def set_lut(self, lut):
+        self.set_transfer_function(lut.table, lut.vmin, lut.vmax)
+
+    def set_camera(self, cam):
+        c = camera_struct(cam)
+        self._check(lib().vr_set_camera(self.ctx, C.byref(c)))
+        self.cam = cam
+
+    # ---- render --------------------------------------------------------
+    def workspace_bytes(self, **kw):
+        p = params_struct(**kw)
+        return int(self._check(lib().vr_render_workspace_bytes(self.ctx, C.byref(p))))
+
+    def render(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, trans="auto",
+               out=None, save=False, workspace=None):
+        p = params_struct(mode, filt, step, ert, trans, save)
+        w, h = self.cam.tile[2], self.cam.tile[3]
+        shape = (h, w, 4) if mode == "composite" else (h, w)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        ws_bytes = int(self._check(lib().vr_render_workspace_bytes(self.ctx, C.byref(p))))
+        if ws_bytes > 0 and (workspace is None or workspace.numel() < ws_bytes):
+            workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        self._check(lib().vr_render(self.ctx, C.byref(p), _ptr(out),
+                                    _ptr(workspace) if ws_bytes > 0 else None, ws_bytes, _stream()))
+        if save:
+            return out, workspace
+        return out
+
+    def render_backward(self, grad_out, workspace, grad_lut=None, grad_vol=None, step=0.5, ert=0.99,
+                        trans="auto"):
+        """Accumulate dL/d(table) and dL/d(voxels) given dL/d(image) and the
+        workspace of a render(save=True) with the same settings."""
+        p = params_struct("composite", "trilinear", step, ert, trans, True)
+        g = grad_out.to(self.device, torch.float32).contiguous()
+        self._check(lib().vr_render_backward(self.ctx, C.byref(p), _ptr(g), _ptr(workspace), workspace.numel(),
+                                             _ptr(grad_lut), _ptr(grad_vol), _stream()))
+        return grad_lut, grad_vol
+
+    def count_samples(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, trans="auto"):
+        p = params_struct(mode, filt, step, ert, trans)
+        w, h = self.cam.tile[2], self.cam.tile[3]
+        counts = torch.empty((h, w), dtype=torch.int32, device=self.device)
+        self._check(lib().vr_count_samples(self.ctx, C.byref(p), _ptr(counts), _stream()))
+        return counts
+
+    def touched_blocks(self, mode="composite", filt="trilinear", step=0.5, ert=0.99):
+        """Number of 8^3 voxel blocks touched by taken samples' footprints."""
+        p = params_struct(mode, filt, step, ert)
+        nbytes = int(self._check(lib().vr_touched_bitmap_bytes(self.ctx)))
+        bits = torch.zeros(nbytes // 4, dtype=torch.int32, device=self.device)
+        self._check(lib().vr_mark_touched_blocks(self.ctx, C.byref(p), _ptr(bits), nbytes, _stream()))
+        b = bits.view(torch.uint8).cpu()
+        return int(torch.bitwise_and(b.unsqueeze(-1) >> torch.arange(8, dtype=torch.uint8), 1).sum())
+
+    # ---- tuning ----------------------------------------------------------
+    def get_tuning(self):
+        t = Tuning()
+        self._check(lib().vr_get_tuning(self.ctx, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = Tuning(**cur)
+        self._check(lib().vr_set_tuning(self.ctx, C.byref(t)))
+
+    # ---- bricks and sort-last compositing ---------------------------------
+    def render_bricks(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, pool=None):
+        """Per-brick partial images of the current viewport.  Returns (parts,
+        pool): parts is a ctypes array of Partial (device pointers into pool)."""
+        p = params_struct(mode, filt, step, ert)
+        need = int(self._check(lib().vr_bricks_pool_bytes(self.ctx, C.byref(p))))
+        if pool is None or pool.numel() < need:
+            pool = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        nb = 1
+        for d, b in zip(self.shape, [self.brick] * 3):
+            nb *= (d + b - 1) // b if b > 0 else 1
+        parts = (Partial * max(nb, 1))()
+        n = C.c_int32()
+        self._check(lib().vr_render_bricks(self.ctx, C.byref(p), parts, len(parts), C.byref(n), _ptr(pool),
+                                           pool.numel(), _stream()))
+        return parts[:n.value], pool
+
+    def brick_order(self, parts):
+        n = len(parts)
+        arr = (Partial * max(n, 1))(*parts)
+        order = (C.c_int32 * max(n, 1))()
+        self._check(lib().vr_brick_order(self.ctx, arr, n, order))
+        return list(order[:n])
+
+    def composite_bricks(self, parts, order, mode="composite", out=None, workspace=None):
+        p = params_struct(mode)
+        n = len(parts)
+        w, h = self.cam.tile[2], self.cam.tile[3]
+        if out is None:
+            out = torch.empty((h, w, 4) if mode == "composite" else (h, w), dtype=torch.float32,
+                              device=self.device)
+        need = int(lib().vr_composite_workspace_bytes(n))
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        arr = (Partial * max(n, 1))(*parts)
+        order_arr = (C.c_int32 * max(n, 1))(*order)
+        self._check(lib().vr_composite_bricks(self.ctx, C.byref(p), arr, order_arr, n, _ptr(out),
+                                              _ptr(workspace), workspace.numel(), _stream()))
+        return out
+
+    def render_bricked(self, mode="composite", filt="trilinear", step=0.5, ert=0.99):
+        """Bricked render: per-brick partials, then the sort-last composite."""
+        parts, pool = self.render_bricks(mode, filt, step, ert)
+        order = self.brick_order(parts)
+        out = self.composite_bricks(parts, order, mode)
+        self._keep = pool
+        return out

@@ -1,0 +1,60 @@
+"""Helpers shared by the GPU parity tests."""
+import sys
+
+import numpy as np
+
+# Tolerances (per element, absolute):
+#  - composite RGBA, FP32 storage: 1e-5 (the stated bar);
+#  - composite RGBA, FP16/BF16 storage against the oracle on the original
+#    FP32 cube: 2e-3; against the oracle on the storage-rounded cube: 1e-5;
+#  - trilinear MIP: the FP32 interpolation of 8 corners in 7 lerps rounds by
+#    at most ~4 ulp of the largest corner (4 * 2^-24 * |V|max, 2.4e-7 |V|max),
+#    the fixed-point position error is below 1e-9 voxel; we allow 1e-6 |s| + 1e-6;
+#  - nearest MIP: bit-exact.
+TOL_COMPOSITE = 1e-5
+TOL_LOWP = 2e-3
+TOL_MIP_REL = 1e-6
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def accept(gpu, res, tol, rel=0.0):
+    """Per element: |gpu - oracle| <= tol (+ rel |oracle|), or, on pixels the
+    oracle flagged as having several correct results, gpu inside [lo, hi]
+    widened by the same tolerance.  Returns (ok_mask, max_err_unflagged)."""
+    out, lo, hi, fl = res["out"], res["lo"], res["hi"], res["flags"]
+    g = np.asarray(gpu, dtype=np.float64)
+    if g.ndim == out.ndim and g.ndim == fl.ndim + 1:
+        flm = fl[..., None] != 0
+    else:
+        flm = fl != 0
+    fin = np.isfinite(out)
+    err = np.where(fin, np.abs(g - np.where(fin, out, 0.0)), np.where(g == out, 0.0, np.inf))
+    t = tol + rel * np.where(fin, np.abs(out), 0.0)
+    ok = err <= t
+    ok |= flm & (g >= lo - t) & (g <= hi + t)
+    ok |= (~fin) & (g == out)
+    unfl = ~np.broadcast_to(flm, err.shape)
+    mx = float(err[unfl].max()) if unfl.any() else 0.0
+    return ok, mx
+
+
+def assert_accept(gpu, res, tol, rel=0.0, what=""):
+    ok, mx = accept(gpu, res, tol, rel)
+    bad = np.argwhere(~ok)
+    log(f"{what}: max err (unflagged) {mx:.3e}, flagged px {(res['flags'] != 0).sum()}, bad {len(bad)}")
+    assert ok.all(), f"{what}: {len(bad)} elements out of tolerance, first {bad[:5].tolist()}"
+    return mx
+
+
+def assert_bitexact_mip(gpu, res, what=""):
+    g = np.asarray(gpu, dtype=np.float64)
+    out, lo, hi, fl = res["out"], res["lo"], res["hi"], res["flags"]
+    clean = fl == 0
+    assert np.array_equal(g[clean], out[clean]), f"{what}: nearest MIP not bit-exact"
+    amb = ~clean
+    assert ((g[amb] >= lo[amb]) & (g[amb] <= hi[amb])).all(), f"{what}: ambiguous pixels outside candidates"
+    log(f"{what}: bit-exact on {clean.sum()} px, {amb.sum()} ambiguous px within candidates")

@@ -1,0 +1,249 @@
+"""GPU parity of the single-pass renderer (vr_render) against the FP64 oracle,
+through the C ABI.  Sizes are small enough for the oracle to finish in
+seconds but span many 64-lane packets, several bricks and ragged edges."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1012_2909_amd import synth
+from tests.gpu_util import (TOL_COMPOSITE, TOL_LOWP, TOL_MIP_REL, assert_accept, assert_bitexact_mip, log)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1012_2909_amd import vr
+    r = vr.Renderer(0)
+    yield r
+    r.close()
+
+
+@pytest.fixture(scope="module")
+def cube64():
+    return synth.make_cube(synth.CUBE_64)
+
+
+def _render(R, vol, lut, cam, storage="f32", brick=0, **kw):
+    R.load_volume(torch.from_numpy(vol), storage=storage, brick=brick)
+    R.set_lut(lut)
+    R.set_camera(cam)
+    img = R.render(**kw)
+    torch.cuda.synchronize()
+    return img.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# the 64^3 case: orthographic view along z, 256x256
+# ---------------------------------------------------------------------------
+def test_axis_view_composite(R, cube64):
+    log("case: 64^3 axis view composite trilinear tau=0.99")
+    lut = synth.lut_ramp()
+    cam = synth.camera_axis_z()
+    img = _render(R, cube64, lut, cam)
+    res = oracle.render(cube64, lut, cam, eps_stop=2e-5)
+    assert_accept(img, res, TOL_COMPOSITE, what="axis composite")
+
+
+def test_axis_view_nearest_mip_bitexact(R, cube64):
+    log("case: 64^3 axis view nearest MIP")
+    cam = synth.camera_axis_z()
+    img = _render(R, cube64, synth.lut_ramp(), cam, mode="mip", filt="nearest")
+    res = oracle.render(cube64, synth.lut_ramp(), cam, mode="mip", filt="nearest")
+    assert_bitexact_mip(img, res, "axis nearest MIP")
+    # and the closed form: per-column maximum
+    ref = np.repeat(np.repeat(cube64.max(axis=0), 4, 0), 4, 1)
+    assert np.array_equal(img, ref)
+
+
+def test_axis_view_trilinear_mip(R, cube64):
+    log("case: 64^3 axis view trilinear MIP")
+    cam = synth.camera_axis_z()
+    img = _render(R, cube64, synth.lut_ramp(), cam, mode="mip")
+    res = oracle.render(cube64, synth.lut_ramp(), cam, mode="mip")
+    assert_accept(img, res, 1e-6, rel=TOL_MIP_REL, what="axis trilinear MIP")
+
+
+def test_axis_view_nearest_composite_and_counts(R, cube64):
+    log("case: 64^3 axis view nearest composite + sample counts")
+    lut = synth.lut_ramp()
+    cam = synth.camera_axis_z()
+    img = _render(R, cube64, lut, cam, filt="nearest")
+    res = oracle.render(cube64, lut, cam, filt="nearest", eps_stop=2e-5)
+    assert_accept(img, res, TOL_COMPOSITE, what="axis nearest composite")
+    cnt = R.count_samples(filt="nearest").cpu().numpy()
+    clean = res["flags"] == 0
+    assert np.array_equal(cnt[clean], res["taken"][clean])
+
+
+# ---------------------------------------------------------------------------
+# perspective orbits, ragged cubes, brick walking
+# ---------------------------------------------------------------------------
+SHAPES = [(64, 64, 64), (29, 50, 37)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("brick", [0, 16, 13])
+@pytest.mark.parametrize("seed", [2, 7])
+def test_orbit_composite(R, shape, brick, seed):
+    log(f"case: orbit composite shape={shape} brick={brick} seed={seed}")
+    vol = synth.make_cube(synth.CubeSpec(shape, 12, seed=seed + 100, fwhm_z=(3.0, 12.0)))
+    lut = synth.lut_ramp()
+    cam = synth.orbit_camera(shape, seed=seed, w=160, h=120)
+    img = _render(R, vol, lut, cam, brick=brick)
+    res = oracle.render(vol, lut, cam, eps_stop=2e-5)
+    assert_accept(img, res, TOL_COMPOSITE, what="orbit composite")
+    # the MIP modes on the same view
+    mipn = R.render(mode="mip", filt="nearest").cpu().numpy()
+    assert_bitexact_mip(mipn, oracle.render(vol, lut, cam, mode="mip", filt="nearest"), "orbit nearest MIP")
+    mipt = R.render(mode="mip").cpu().numpy()
+    assert_accept(mipt, oracle.render(vol, lut, cam, mode="mip"), 1e-6, rel=TOL_MIP_REL, what="orbit tri MIP")
+
+
+@pytest.mark.parametrize("trans", ["product", "log", "auto"])
+def test_long_rays_no_early_stop(R, trans):
+    """Deep traversal (alpha / 64, no early stop): every ray runs its whole
+    chord; both transmittance forms meet the bar."""
+    log(f"case: long rays trans={trans}")
+    shape = (96, 80, 72)
+    vol = synth.make_cube(synth.CubeSpec(shape, 20, seed=31, fwhm_z=(5.0, 30.0)))
+    lut = synth.lut_ramp(alpha_scale=1 / 64)
+    cam = synth.orbit_camera(shape, seed=3, w=96, h=72)
+    img = _render(R, vol, lut, cam, ert=1.0, trans=trans)
+    res = oracle.render(vol, lut, cam, tau=1.0)
+    assert_accept(img, res, TOL_COMPOSITE, what=f"long rays {trans}")
+
+
+def test_layouts_agree_bitwise(R):
+    """The arithmetic does not depend on the brick layout."""
+    shape = (40, 33, 47)
+    vol = synth.make_cube(synth.CubeSpec(shape, 8, seed=5))
+    lut = synth.lut_random(9)
+    cam = synth.orbit_camera(shape, seed=11, w=128, h=96)
+    imgs = [_render(R, vol, lut, cam, brick=b) for b in (0, 8, 16, 21)]
+    for im in imgs[1:]:
+        assert np.array_equal(im, imgs[0])
+
+
+TUNES = [dict(path=1), dict(path=1, packet_w=8, packet_h=8, waves_per_group=8),
+         dict(path=2, packet_w=8, packet_h=8), dict(path=2, packet_w=64, packet_h=1),
+         dict(path=2, packet_w=4, packet_h=16), dict(path=2, lds_kib=8, slab_max=4),
+         dict(path=2, slab_max=1), dict(path=2, lds_kib=48, slab_max=64),
+         dict(path=2, lds_kib=144, slab_max=32), dict(path=1, unroll=2), dict(path=1, unroll=4),
+         dict(path=1, unroll=4, packet_w=64, packet_h=1),
+         dict(path=1, copy=0), dict(path=1, copy=1), dict(path=1, copy=2, unroll=2),
+         dict(path=2, copy=0), dict(path=2, copy=1), dict(path=2, copy=2, lds_kib=96),
+         dict(path=2, copy=1, lds_kib=8, slab_max=2)]
+
+
+@pytest.mark.parametrize("mode,filt", [("composite", "trilinear"), ("mip", "nearest"), ("mip", "trilinear")])
+def test_paths_and_shapes_agree_bitwise(R, mode, filt):
+    """Direct gathers and LDS-staged boxes, every bundle shape and slab
+    budget (including ones that force the fallbacks) give identical images."""
+    shape = (70, 45, 52)
+    vol = synth.make_cube(synth.CubeSpec(shape, 10, seed=17, fwhm_z=(4.0, 20.0)))
+    lut = synth.lut_ramp(alpha_scale=0.25)
+    cams = [synth.orbit_camera(shape, seed=s, w=150, h=110) for s in (1, 8)] + [
+        synth.Camera(synth.ORTHO, (-40.0, 30.0, 20.0), (26.0, 22.5, 35.0), (0.0, -1.0, 0.0),
+                     half_w=50.0, half_h=40.0, full_w=150, full_h=110)]
+    R.load_volume(torch.from_numpy(vol))
+    R.set_lut(lut)
+    base_t = R.get_tuning()
+    try:
+        for cam in cams:
+            R.set_camera(cam)
+            R.set_tuning(**base_t)
+            ref = R.render(mode=mode, filt=filt).cpu().numpy()
+            o = oracle.render(vol, lut, cam, mode=mode, filt=filt, eps_stop=2e-5)
+            if filt == "nearest":
+                assert_bitexact_mip(ref, o, "paths ref")
+            else:
+                assert_accept(ref, o, TOL_COMPOSITE if mode == "composite" else 1e-6,
+                              rel=0 if mode == "composite" else TOL_MIP_REL, what="paths ref")
+            for t in TUNES:
+                R.set_tuning(**{**base_t, **t})
+                img = R.render(mode=mode, filt=filt).cpu().numpy()
+                assert np.array_equal(img, ref), f"tuning {t} differs"
+    finally:
+        R.set_tuning(**base_t)
+
+
+def test_tile_stitching_bitexact(R, cube64):
+    """5x5 viewports of one frame, stitched, equal the full-frame render."""
+    lut = synth.lut_ramp()
+    cam = synth.orbit_camera(cube64.shape, seed=4, w=5 * 48, h=5 * 27)
+    full = _render(R, cube64, lut, cam)
+    st = np.zeros_like(full)
+    for t in synth.tiles_5x5(cam, 48, 27):
+        R.set_camera(t)
+        x0, y0, w, h = t.tile
+        st[y0:y0 + h, x0:x0 + w] = R.render().cpu().numpy()
+    assert np.array_equal(st, full)
+
+
+def test_eye_inside_cube(R, cube64):
+    lut = synth.lut_ramp(alpha_scale=0.25)
+    cam = synth.Camera(synth.PERSPECTIVE, (30.0, 33.0, 20.0), (40.0, 20.0, 50.0), (0.0, -1.0, 0.0),
+                       fovy_deg=70.0, full_w=96, full_h=64)
+    img = _render(R, cube64, lut, cam)
+    res = oracle.render(cube64, lut, cam, eps_stop=2e-5)
+    assert_accept(img, res, TOL_COMPOSITE, what="eye inside")
+
+
+def test_degenerate_sizes(R):
+    # one-voxel-thin cube, 1x1 viewport, a viewport that misses the cube
+    vol = synth.make_cube(synth.CubeSpec((1, 5, 7), 1, seed=8))
+    lut = synth.lut_ramp()
+    cam = synth.Camera(synth.ORTHO, (3.5, 2.5, -4.0), (3.6, 2.4, 0.5), (0.0, -1.0, 0.0),
+                       half_w=4.0, half_h=3.0, full_w=40, full_h=30)
+    img = _render(R, vol, lut, cam)
+    assert_accept(img, oracle.render(vol, lut, cam, eps_stop=2e-5), TOL_COMPOSITE, what="thin cube")
+    one = cam.with_tile(17, 11, 1, 1)
+    R.set_camera(one)
+    px = R.render().cpu().numpy()
+    assert np.allclose(px[0, 0], img[11, 17], atol=0, rtol=0)
+    miss = synth.Camera(synth.ORTHO, (100.0, 100.0, -4.0), (100.0, 100.0, 0.0), (0.0, -1.0, 0.0),
+                        half_w=2.0, half_h=2.0, full_w=8, full_h=8)
+    R.set_camera(miss)
+    assert (R.render().cpu().numpy() == 0).all()
+    assert np.isneginf(R.render(mode="mip").cpu().numpy()).all()
+
+
+# ---------------------------------------------------------------------------
+# FP16 / BF16 storage
+# ---------------------------------------------------------------------------
+def _dequant(vol, storage):
+    t = torch.from_numpy(vol)
+    if storage == "f16":
+        return t.to(torch.float16).to(torch.float32).numpy()
+    return t.to(torch.bfloat16).to(torch.float32).numpy()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_low_precision_storage(R, storage):
+    log(f"case: storage {storage}")
+    shape = (64, 48, 56)
+    vol = synth.make_cube(synth.CubeSpec(shape, 16, seed=12, fwhm_z=(5.0, 30.0)))
+    lut = synth.lut_ramp()
+    cam = synth.orbit_camera(shape, seed=6, w=128, h=96)
+    img = _render(R, vol, lut, cam, storage=storage, brick=24)
+    deq = _dequant(vol, storage)
+    # arithmetic error alone: against the oracle on the rounded cube
+    assert_accept(img, oracle.render(deq, lut, cam, eps_stop=2e-5), TOL_COMPOSITE, what=f"{storage} vs rounded cube")
+    # total error against the original FP32 cube
+    res = oracle.render(vol, lut, cam, eps_stop=2e-5)
+    ok_mask_err = np.abs(img - res["out"])
+    flagged = res["flags"] != 0
+    mx = float(ok_mask_err[~flagged].max())
+    log(f"{storage} vs fp32 cube: max abs {mx:.3e}")
+    if storage == "f16":
+        assert mx <= TOL_LOWP
+    else:
+        # BF16 keeps 8 mantissa bits: a bright voxel (|v| in [8,16)) is rounded
+        # by up to 2^-5, i.e. 2.4e-3 of the table's range; report, bound loosely
+        assert mx <= 4 * TOL_LOWP
+    # MIP nearest on rounded storage is bit-exact against the rounded cube
+    R.set_camera(cam)
+    mipn = R.render(mode="mip", filt="nearest").cpu().numpy()
+    assert_bitexact_mip(mipn, oracle.render(deq, lut, cam, mode="mip", filt="nearest"), f"{storage} nearest MIP")
