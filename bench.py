@@ -1,19 +1,21 @@
 """Throughput of the ray caster on the 8 GiB spectral cube at 1920x1080.
 
-One step renders one 1920x1080 frame of the 1024x1024x2048 float32 cube
-(noise + 500 sources) from a perspective orbit camera (seed 2, fovy 30,
-step 0.5 voxel) in both modes: composite (256-entry grey ramp over
-[-3, 10], early stop at alpha 0.99) and maximum-intensity projection
-(trilinear).  Inputs are resident in HBM before the timed region; the
-volume layout (transcode) is timed separately.  Prints one JSON line.
+Workload: the 1024x1024x2048 float32 cube (noise + 500 sources, seed 2),
+1920x1080 perspective orbit cameras (fovy 30, bounding-sphere fit) at 16
+seeded orbit angles, step 0.5 voxel.  One step renders one frame (the next
+angle) in both modes: composite (256-entry grey ramp over [-3, 10], early
+stop at alpha 0.99) and trilinear maximum-intensity projection.  Inputs are
+resident in HBM before the timed region; the volume layout (transcode) is
+timed separately.  Launch shapes come from the library's autotuner (one
+search per mode on the first angle).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu]
+  python bench.py [--gpus 1] [--steps 16] [--warmup 2] [--no-cpu]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,26 +27,45 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+N_ANGLES = 16
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def angle_seeds():
+    return [int(s) for s in np.random.default_rng(2).integers(0, 2**31 - 1, N_ANGLES)]
+
+
+def kernel_revision():
+    """Hash of the kernels' sources: stored traffic counters are only valid
+    for the revision they were measured on."""
+    h = hashlib.sha1()
+    for f in ("k_slab.hip", "k_march.hip", "vr_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1012_2909_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
-    ap.add_argument("--brick", type=int, default=0, help="brick edge of the layout (0 = one brick)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shapes")
+    ap.add_argument("--tune-cache", default="/tmp/vrcube_tune.json", help="autotuner cache file ('' for none)")
+    ap.add_argument("--measure-cache", default="/tmp/vrcube_bench_measure.json",
+                    help="cache of the per-angle sample counts and touched blocks ('' for none)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sort-last exchange "
-              f"is a design, not a build", file=sys.stderr, flush=True)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU sort-last exchange is "
+              f"described in the design notes, not built", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import torch
@@ -52,13 +73,21 @@ def main():
     from paper_1012_2909_amd import synth, vr
 
     dev = torch.device("cuda", 0)
+    if args.copy_probe:
+        a = torch.ones(1 << 29, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 4 copies of 2 GiB (2 GiB read + 2 GiB written each)")
+        return
     spec = synth.CUBE_8GIB
     W, H = 1920, 1080
     step = 0.5
     t = time.time()
     vol = synth.make_cube(spec)
     log(f"cube {spec.shape} generated in {time.time() - t:.1f}s")
-    cam = synth.orbit_camera(spec.shape, seed=2, w=W, h=H)
+    cams = [synth.orbit_camera(spec.shape, seed=s, w=W, h=H) for s in angle_seeds()]
     lut = synth.lut_ramp()
 
     R = vr.Renderer(0)
@@ -66,88 +95,123 @@ def main():
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    R.load_volume(src, storage=args.storage, brick=args.brick)
+    R.load_volume(src, storage=args.storage, brick=0, orientations=3)
     e1.record()
     torch.cuda.synchronize()
     load_ms = e0.elapsed_time(e1)
+    esz = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
     store_bytes = R.storage.numel()
     load_gbs = (vol.nbytes + store_bytes) / (load_ms * 1e-3) / 1e9
-    log(f"layout transcode {load_ms:.2f} ms ({load_gbs:.0f} GB/s moved)")
+    log(f"layout transcode (3 orientation copies, {store_bytes / 1e9:.1f} GB) {load_ms:.2f} ms, {load_gbs:.0f} GB/s moved")
     del src
     torch.cuda.empty_cache()
     R.set_lut(lut)
-    R.set_camera(cam)
 
-    modes = [("composite", dict(mode="composite", filt="trilinear", step=step, ert=0.99)),
-             ("mip", dict(mode="mip", filt="trilinear", step=step, ert=0.99))]
+    modes = {"composite": dict(mode="composite", filt="trilinear", step=step, ert=0.99),
+             "mip": dict(mode="mip", filt="trilinear", step=step, ert=0.99)}
     outs = {"composite": torch.empty((H, W, 4), dtype=torch.float32, device=dev),
             "mip": torch.empty((H, W), dtype=torch.float32, device=dev)}
 
-    # measurement passes (not timed): samples per frame and touched blocks
-    samples, touched = {}, {}
-    for name, kw in modes:
-        c = R.count_samples(**{k: v for k, v in kw.items()})
-        samples[name] = int(c.to(torch.int64).sum().item())
-        touched[name] = R.touched_blocks(mode=kw["mode"], filt=kw["filt"], step=step, ert=kw["ert"])
-        log(f"{name}: {samples[name] / 1e9:.3f} G samples/frame, {touched[name]} touched 8^3 blocks")
+    # launch shapes per mode (autotuned on the first angle)
+    tunes = {}
+    R.set_camera(cams[0])
+    for name, kw in modes.items():
+        if args.no_tune:
+            tunes[name] = R.get_tuning()
+        else:
+            tunes[name] = R.autotune(mode=kw["mode"], filt=kw["filt"], step=step, ert=kw["ert"],
+                                     cache_path=args.tune_cache or None)
+        log(f"{name}: launch shape {tunes[name]}")
 
-    esz = {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
+    # measurement passes (not timed): samples per frame and touched blocks per
+    # angle.  Cached per source revision so that a profiled rerun holds only
+    # the timed launches.
+    mkey = f"{kernel_revision()}|{args.storage}|{spec.shape}|{W}x{H}|{step}"
+    mpath = args.measure_cache
+    samples = touched = None
+    if mpath and os.path.exists(mpath):
+        try:
+            m = json.load(open(mpath))
+            if m.get("key") == mkey:
+                samples, touched = m["samples"], m["touched"]
+                log(f"sample counts and touched blocks from {mpath}")
+        except (OSError, ValueError, KeyError):
+            samples = touched = None
+    if samples is None:
+        samples = {n: [] for n in modes}
+        touched = {n: [] for n in modes}
+        for c in cams:
+            R.set_camera(c)
+            for name, kw in modes.items():
+                R.set_tuning(**tunes[name])
+                samples[name].append(int(R.count_samples(**kw).to(torch.int64).sum().item()))
+                touched[name].append(R.touched_blocks(mode=kw["mode"], filt=kw["filt"], step=step, ert=kw["ert"]))
+        if mpath:
+            with open(mpath, "w") as f:
+                json.dump({"key": mkey, "samples": samples, "touched": touched}, f)
+    for name in modes:
+        log(f"{name}: {np.mean(samples[name]) / 1e9:.3f} G samples/frame (mean of {N_ANGLES} angles), "
+            f"{np.mean(touched[name]):.0f} touched 8^3 blocks")
     out_bytes = {"composite": W * H * 16, "mip": W * H * 4}
-    alg_bytes = {n: touched[n] * 512 * esz + out_bytes[n] + (lut.table.nbytes if n == "composite" else 0)
-                 for n, _ in modes}
+    alg_bytes = {n: [b * 512 * esz + out_bytes[n] + (lut.table.nbytes if n == "composite" else 0)
+                     for b in touched[n]] for n in modes}
 
-    def run_step(evs=None):
-        for i, (name, kw) in enumerate(modes):
+    def run_step(k, evs=None):
+        R.set_camera(cams[k % N_ANGLES])
+        for name, kw in modes.items():
+            R.set_tuning(**tunes[name])
             if evs is not None:
                 evs[name][0].record()
             R.render(out=outs[name], **kw)
             if evs is not None:
                 evs[name][1].record()
 
-    for _ in range(args.warmup):
-        run_step()
+    for k in range(args.warmup):
+        run_step(k)
     torch.cuda.synchronize()
-
-    per_launch = {n: [] for n, _ in modes}
-    ev_sets = [{n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n, _ in modes}
-               for _ in range(args.steps)]
+    ev = [{n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in modes}
+          for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        run_step(ev_sets[k])
+        run_step(k, ev[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    for k in range(args.steps):
-        for n, _ in modes:
-            per_launch[n].append(ev_sets[k][n][0].elapsed_time(ev_sets[k][n][1]))
+    per_launch = {n: [ev[k][n][0].elapsed_time(ev[k][n][1]) for k in range(args.steps)] for n in modes}
     ms_step = wall * 1e3 / args.steps
-    total_samples = samples["composite"] + samples["mip"]
-    value = total_samples / (ms_step * 1e-3) / 1e9
+    total_samples = sum(samples[n][k % N_ANGLES] for n in modes for k in range(args.steps))
+    value = total_samples / wall / 1e9
     mean_ms = {n: float(np.mean(v)) for n, v in per_launch.items()}
     fps = {n: 1e3 / mean_ms[n] for n in mean_ms}
-    gsps = {n: samples[n] / (mean_ms[n] * 1e-3) / 1e9 for n in mean_ms}
+    gsps = {n: sum(samples[n][k % N_ANGLES] for k in range(args.steps)) / (sum(per_launch[n]) * 1e-3) / 1e9
+            for n in modes}
+    frac = {n: float(np.mean([alg_bytes[n][k % N_ANGLES] / (per_launch[n][k] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                              for k in range(args.steps)])) for n in modes}
     log(f"step {ms_step:.3f} ms; per launch {mean_ms}; fps {fps}")
 
-    # roofline of the dominant kernel (the MIP march over the whole cube)
+    # roofline of the dominant kernel: the MIP march over the whole cube
     dom = max(mean_ms, key=mean_ms.get)
-    achieved = alg_bytes[dom] / (mean_ms[dom] * 1e-3) / 1e9
+    alg_per_launch = float(np.mean([alg_bytes[dom][k % N_ANGLES] for k in range(args.steps)]))
+    achieved = alg_per_launch / (mean_ms[dom] * 1e-3) / 1e9
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         try:
             tr = json.load(open(tf))
-            key = f"{dom}_{args.storage}_b{args.brick}"
-            if key in tr and tr[key].get("kernel_rev") == kernel_revision():
-                traffic = tr[key]["bytes_per_launch"]
-        except Exception:
+            e = tr.get(f"{dom}_{args.storage}")
+            if e and e.get("kernel_rev") == kernel_revision():
+                traffic = e["bytes_per_launch"]
+        except (OSError, ValueError, KeyError):
             traffic = None
+    kname = {"mip": "k_slab<MIP>" if tunes["mip"]["path"] != 1 else "k_march<MIP>",
+             "composite": "k_march<COMPOSITE>" if tunes["composite"]["path"] != 2 else "k_slab<COMPOSITE>"}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": f"k_march<{args.storage},{dom}>", "algorithmic_bytes": alg_bytes[dom]}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname[dom],
+            "algorithmic_bytes_per_launch": int(alg_per_launch)}
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(vol, lut, cam, step, args.cpu_seconds)
+        cpu = cpu_baseline(vol, lut, cams[0], step, args.cpu_seconds)
 
     rec = {
         "metric": "G ray-samples/s + fps at 1920x1080 on 8 GiB cube; % HBM roofline",
@@ -162,14 +226,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.storage == "f32" else f"{args.storage}-storage/f32",
         "data": "synthetic",
-        "config": {"workload": "1024x1024x2048 float32 cube (8 GiB), 1920x1080 perspective orbit (seed 2), "
-                               "step 0.5; composite (ramp table, stop at alpha 0.99) + trilinear MIP",
-                   "brick": args.brick, "storage": args.storage, "frames_per_step": 2},
+        "config": {"workload": "1024x1024x2048 float32 cube (8 GiB, noise + 500 sources), 1920x1080 perspective "
+                               f"orbit cameras at {N_ANGLES} seeded angles, step 0.5 voxel; per step one frame in "
+                               "composite (ramp table, stop at alpha 0.99) and trilinear MIP",
+                   "storage": args.storage, "frames_per_step": 2, "orientation_copies": 3},
         "fps": {k: round(v, 2) for k, v in fps.items()},
         "gsamples_per_s": {k: round(v, 2) for k, v in gsps.items()},
-        "samples_per_frame": samples,
-        "hbm_roofline_frac": {n: round(alg_bytes[n] / (mean_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) for n in mean_ms},
-        "load_volume": {"ms": round(load_ms, 3), "GBps": round(load_gbs, 1)},
+        "samples_per_frame_mean": {n: int(np.mean(samples[n])) for n in modes},
+        "hbm_roofline_frac": {n: round(v, 4) for n, v in frac.items()},
+        "launch_shapes": tunes,
+        "load_volume": {"ms": round(load_ms, 3), "GBps_moved": round(load_gbs, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -177,40 +243,29 @@ def main():
     R.close()
 
 
-def kernel_revision():
-    """Hash of the march kernel's source; traffic counters are only valid for it."""
-    import hashlib
-    h = hashlib.sha1()
-    for f in ("k_march.hip", "vr_common.h"):
-        h.update(open(os.path.join(ROOT, "paper_1012_2909_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:12]
-
-
 def cpu_baseline(vol, lut, cam, step, seconds):
-    """The FP64 oracle on a bounded, seeded sample of the same frame's pixels
+    """The FP64 oracle on a bounded, seeded sample of the first angle's pixels
     (both modes), timed on the host cores."""
     import oracle
-    threads = min(os.cpu_count() or 1, 64)
-    rng = np.random.default_rng(12345)
+    threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0")) or 64))
     W, H = cam.tile[2], cam.tile[3]
-    # probe on a small sample to size the real one
-    n_probe = 400
-    pix = np.stack([rng.integers(0, W, n_probe), rng.integers(0, H, n_probe)], 1).astype(np.int32)
+    rng = np.random.default_rng(12345)
+    # size the sample from a probe of pixels that hit the cube (misses cost nothing)
+    probe = np.stack([rng.integers(0, W, 2000), rng.integers(0, H, 2000)], 1).astype(np.int32)
     t = time.perf_counter()
-    a = oracle.render(vol, lut, cam, mode="mip", pixels=pix, step=step, threads=threads)
-    b = oracle.render(vol, lut, cam, pixels=pix, step=step, threads=threads)
-    dt = time.perf_counter() - t
-    per_px = max(dt / n_probe, 1e-7)
-    n = int(min(W * H, max(1000, seconds / per_px)))
+    oracle.render(vol, lut, cam, mode="mip", pixels=probe, step=step, threads=threads)
+    oracle.render(vol, lut, cam, pixels=probe, step=step, threads=threads)
+    per_px = max((time.perf_counter() - t) / len(probe), 1e-8)
+    n = int(min(W * H, max(2000, seconds / per_px)))
     pix = np.stack([rng.integers(0, W, n), rng.integers(0, H, n)], 1).astype(np.int32)
-    log(f"cpu baseline: oracle on {n} sampled pixels x 2 modes, {threads} threads")
+    log(f"cpu baseline: FP64 oracle on {n} seeded pixels x 2 modes, {threads} threads")
     t = time.perf_counter()
     a = oracle.render(vol, lut, cam, mode="mip", pixels=pix, step=step, threads=threads)
     b = oracle.render(vol, lut, cam, pixels=pix, step=step, threads=threads)
     dt = time.perf_counter() - t
     s = int(a["taken"].sum() + b["taken"].sum())
     return {"value": round(s / dt / 1e9, 5), "unit": "G ray-samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} seeded pixels of the 1920x1080 frame, MIP + composite, {s} samples in {dt:.1f}s"}
+            "sample": f"{n} seeded pixels of the first 1920x1080 angle, MIP + composite: {s} samples in {dt:.1f}s"}
 
 
 if __name__ == "__main__":

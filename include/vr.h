@@ -132,6 +132,8 @@ typedef struct {
     int32_t slab_max;             /* LDS-staged path: thickest slab tried, 1..64 voxels */
     int32_t copy;                 /* layouts with 3 orientation copies: -1 auto (fastest axis along the
                                      image rows), 0/1/2 force the x/y/z-fastest copy */
+    int32_t order;                /* tile order: 0 one contiguous band of tiles per XCD (L2 reuse),
+                                     1 hardware order (work spread evenly over the XCDs) */
 } vr_tuning;
 
 /* ---- context ---------------------------------------------------------- */
@@ -271,6 +273,10 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *params, const vr_view *
                     float vmin, float vmax, void *workspace_dev, int64_t ws_bytes,
                     int32_t use_graph, void *stream);
 
+/* Graphs captured so far by vr_render_batch on this context (a replay with
+ * unchanged launch arguments does not capture again). */
+int vr_batch_graph_captures(const vr_ctx *ctx);
+
 /* ---- tuning ------------------------------------------------------------- */
 
 /* Current launch shape, and an explicit override (validated). */
@@ -284,6 +290,13 @@ int vr_set_tuning(vr_ctx *ctx, const vr_tuning *t);
  * the search.  Synchronises the stream. */
 int vr_autotune(vr_ctx *ctx, const vr_render_params *params, float *out_dev, void *workspace_dev,
                 int64_t ws_bytes, const char *cache_path, void *stream);
+
+/* The same search for vr_render_batch over these views (bundle shape, LDS
+ * budget, slab thickness and persistent workgroups per CU), keyed by the
+ * batch's total pixel count bucket.  Renders into the views' outputs. */
+int vr_autotune_batch(vr_ctx *ctx, const vr_render_params *params, const vr_view *views, int32_t n_views,
+                      const float *luts_dev, int32_t n_luts, int32_t lut_n, float vmin, float vmax,
+                      void *workspace_dev, int64_t ws_bytes, const char *cache_path, void *stream);
 
 #ifdef __cplusplus
 }

@@ -82,7 +82,7 @@ template <typename S, int MODE, int FILTER, bool SINGLE>
 __global__ __launch_bounds__(512) void k_march(MarchArgs A) {
     __shared__ float4 lut[1024];
     int px, py;
-    uint32_t group = xcd_remap(blockIdx.x, gridDim.x);
+    uint32_t group = tile_order(blockIdx.x, gridDim.x, A.order);
     const bool valid = lane_pixel(A, group, px, py);
     int64_t pix = (int64_t)py * A.cam.tile_w + px;
 
@@ -141,7 +141,7 @@ template <typename S, int MODE, int FILTER, int U>
 __global__ __launch_bounds__(256) void k_march_u(MarchArgs A) {
     __shared__ float4 lut[1024];
     int px, py;
-    uint32_t group = xcd_remap(blockIdx.x, gridDim.x);
+    uint32_t group = tile_order(blockIdx.x, gridDim.x, A.order);
     const bool valid = lane_pixel(A, group, px, py);
     const int64_t pix = (int64_t)py * A.cam.tile_w + px;
     const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;

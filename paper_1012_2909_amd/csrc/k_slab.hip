@@ -251,18 +251,15 @@ __device__ __forceinline__ void run_slabs(const SlabArgs &SA, const Frustum &F, 
     }
 }
 
+// One bundle of bw x bh pixels whose top-left pixel is (bx0, by0) of the
+// viewport in SA.m (called by every thread of the workgroup).  smem holds the
+// table (composite) followed by the voxel box; red is a 16-int scratch.
 template <typename S, int MODE, int FILTER, int ORI>
-__global__ __launch_bounds__(256) void k_slab(SlabArgs SA) {
-    extern __shared__ float smem[];
-    __shared__ int32_t red[16];
+__device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0, float *smem, int32_t *red) {
     const MarchArgs &A = SA.m;
     const int tid = threadIdx.x;
     float4 *lut = (float4 *)smem;                               // composite: n entries
     float *box = smem + (MODE == VR_COMPOSITE ? 4 * A.lut.n : 0);
-
-    const uint32_t group = xcd_remap(blockIdx.x, gridDim.x);
-    const int gbx = group % A.groups_x, gby = group / A.groups_x;
-    const int bx0 = gbx * SA.bw, by0 = gby * SA.bh;
     const int px = bx0 + tid % SA.bw, py = by0 + tid / SA.bw;
     const bool valid = px < A.cam.tile_w && py < A.cam.tile_h;
     const VolDev &V = A.vol;
@@ -382,13 +379,112 @@ __global__ __launch_bounds__(256) void k_slab(SlabArgs SA) {
             if (!go) break;
         }
     }
-    if (!valid) return;
-    if (A.out) {
-        if (MODE == VR_MIP) ((float *)A.out)[pix] = ls.m;
-        else ((float4 *)A.out)[pix] = make_float4(ls.C0, ls.C1, ls.C2, 1.0f - ls.T);
+    if (valid) {
+        if (A.out) {
+            if (MODE == VR_MIP) ((float *)A.out)[pix] = ls.m;
+            else ((float4 *)A.out)[pix] = make_float4(ls.C0, ls.C1, ls.C2, 1.0f - ls.T);
+        }
+        if (A.counts) A.counts[pix] = ls.k;
+        if (A.taken) A.taken[pix] = ls.k;
     }
-    if (A.counts) A.counts[pix] = ls.k;
-    if (A.taken) A.taken[pix] = ls.k;
+}
+
+template <typename S, int MODE, int FILTER, int ORI>
+__global__ __launch_bounds__(256) void k_slab(SlabArgs SA) {
+    extern __shared__ float smem[];
+    __shared__ int32_t red[16];
+    const uint32_t group = tile_order(blockIdx.x, gridDim.x, SA.m.order);
+    const int gbx = group % SA.m.groups_x, gby = group / SA.m.groups_x;
+    slab_bundle<S, MODE, FILTER, ORI>(SA, gbx * SA.bw, gby * SA.bh, smem, red);
+}
+
+// K6: persistent workgroups pull bundles from an atomic queue until every
+// bundle of every view is done (each workgroup exits once the counter passes
+// the item count).  Items are numbered view by view, largest views first.
+template <typename S, int MODE, int FILTER>
+__global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
+    extern __shared__ float smem[];
+    __shared__ int32_t red[16];
+    __shared__ int32_t item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int32_t)atomicAdd(B.queue, 1u);
+        __syncthreads();
+        const int32_t item = item_s;
+        __syncthreads();
+        if (item >= B.total_items) break;
+        int32_t lo = 0, hi = B.n_views - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (B.views[mid].tile_begin <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const ViewDev &V = B.views[lo];
+        SlabArgs SA{};
+        SA.m.cam = V.cam;
+        SA.m.vol = B.vol;
+        apply_copy(SA.m.vol, V.ori);
+        SA.m.lut.rgba = B.luts + (int64_t)V.lut_index * B.lut_n;
+        SA.m.lut.n = B.lut_n;
+        SA.m.lut.vmin = B.vmin;
+        SA.m.lut.scale = B.scale;
+        SA.m.step = B.step;
+        SA.m.thr = B.thr;
+        SA.m.ert = B.ert;
+        SA.m.trans = B.trans;
+        SA.m.out = V.out;
+        SA.m.groups_x = V.tiles_x;
+        SA.bw = B.bw;
+        SA.bh = B.bh;
+        SA.cap = B.cap;
+        SA.lmax = B.lmax;
+        const int32_t t = item - V.tile_begin;
+        const int bx0 = (t % V.tiles_x) * B.bw, by0 = (t / V.tiles_x) * B.bh;
+        if (V.ori == 1) slab_bundle<S, MODE, FILTER, 1>(SA, bx0, by0, smem, red);
+        else if (V.ori == 2) slab_bundle<S, MODE, FILTER, 2>(SA, bx0, by0, smem, red);
+        else slab_bundle<S, MODE, FILTER, 0>(SA, bx0, by0, smem, red);
+        __syncthreads();   // the table and box in LDS are rewritten by the next item
+    }
+}
+
+__global__ void k_reset_u32(uint32_t *p, int32_t n) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_reset_u32(uint32_t *p, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <typename S, int MODE, int FILTER>
+static hipError_t launch_batch_t(const BatchArgs &a, int32_t groups, hipStream_t s) {
+    const size_t lds = (size_t)a.cap * 4 + (MODE == VR_COMPOSITE ? (size_t)a.lut_n * 16 : 0);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch<S, MODE, FILTER>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_batch<S, MODE, FILTER>), dim3((unsigned)groups), dim3((unsigned)(a.bw * a.bh)), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_batch_s(const BatchArgs &a, int32_t mode, int32_t filter, int32_t groups, hipStream_t s) {
+    if (mode == VR_MIP) {
+        if (filter == VR_NEAREST) return launch_batch_t<S, VR_MIP, VR_NEAREST>(a, groups, s);
+        return launch_batch_t<S, VR_MIP, VR_TRILINEAR>(a, groups, s);
+    }
+    if (filter == VR_NEAREST) return launch_batch_t<S, VR_COMPOSITE, VR_NEAREST>(a, groups, s);
+    return launch_batch_t<S, VR_COMPOSITE, VR_TRILINEAR>(a, groups, s);
+}
+
+hipError_t launch_batch(const BatchArgs &a, int32_t mode, int32_t filter, int32_t groups, hipStream_t s) {
+    if (groups <= 0 || a.total_items <= 0) return hipSuccess;
+    switch (a.vol.dtype) {
+        case VR_F32: return launch_batch_s<float>(a, mode, filter, groups, s);
+        case VR_F16: return launch_batch_s<_Float16>(a, mode, filter, groups, s);
+        default: return launch_batch_s<bf16_t>(a, mode, filter, groups, s);
+    }
 }
 
 template <typename S, int MODE, int FILTER, int ORI>

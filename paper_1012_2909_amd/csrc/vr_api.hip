@@ -29,6 +29,8 @@ int vr_fail(const vr_ctx *ctx, int code, const char *fmt, ...) {
 }
 #define fail vr_fail
 
+int64_t vr_align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
 static int ok(vr_ctx *ctx) {
     if (ctx) ctx->err.clear();
     return VR_OK;
@@ -190,20 +192,25 @@ MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const CamDev &ca
     a.waves = ctx->tune.waves_per_group;
     a.groups_x = (cam.tile_w + a.packet_w - 1) / a.packet_w;
     a.unroll = ctx->tune.unroll;
+    a.order = ctx->tune.order;
     select_copy(a.vol, cam, ctx->tune.copy);
     return a;
 }
 
-// The LDS-staged kernel serves one-brick layouts (the padded cube); the
-// direct-gather kernel walks multi-brick layouts and serves as the fallback.
-static bool use_slab_path(const vr_ctx *ctx) {
+// The LDS-staged kernel serves one-brick layouts; the direct-gather kernel
+// walks multi-brick layouts and serves as the fallback.  Automatic choice:
+// long rays (MIP, or composite without early termination) stage voxel boxes
+// in LDS; early-terminating composites, whose rays stop after a few samples,
+// gather directly.
+static bool use_slab_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single) return false;
-    if (ctx->tune.path == 1) return false;
-    return ctx->tune.waves_per_group == 4;
+    if (ctx->tune.path == 1 || ctx->tune.waves_per_group != 4) return false;
+    if (ctx->tune.path == 2) return true;
+    return p->mode == VR_MIP || p->ert_alpha >= 1.0f;
 }
 
 static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s) {
-    if (use_slab_path(ctx)) {
+    if (use_slab_path(ctx, p)) {
         int32_t cap = ctx->tune.lds_kib * 1024 / 4;
         return launch_slab(a, p->mode, p->filter, a.packet_w, a.packet_h * a.waves, cap, ctx->tune.slab_max, s);
     }
@@ -238,12 +245,16 @@ int vr_create(vr_ctx **out, int device) {
     vr_ctx *c = new (std::nothrow) vr_ctx();
     if (!c) return fail(nullptr, VR_ENOMEM, "out of host memory");
     c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
     *out = c;
     return VR_OK;
 }
 
 int vr_destroy(vr_ctx *ctx) {
     if (!ctx) return VR_OK;
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
     if (ctx->graph_src) (void)hipGraphDestroy(ctx->graph_src);
     if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
@@ -293,27 +304,9 @@ static bool layout_of(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32
     return true;
 }
 
-// The copy whose fastest axis runs along the image rows (largest |r_a|): a
-// ray packet spreads mostly along r, so its lanes then share cache lines.
 static void select_copy(VolDev &v, const CamDev &c, int32_t forced) {
     if (v.orients < 3) return;
-    int o = 0;
-    if (forced >= 0 && forced <= 2) o = forced;
-    else {
-        if (std::fabs(c.r[1]) > std::fabs(c.r[o])) o = 1;
-        if (std::fabs(c.r[2]) > std::fabs(c.r[o])) o = 2;
-    }
-    int64_t pf, pm, ps;
-    copy_pitches(v, o, pf, pm, ps);
-    int64_t st[3];
-    st[o] = 1;
-    st[(o + 1) % 3] = pf;
-    st[(o + 2) % 3] = pf * pm;
-    v.data = (const char *)v.data + v.copy_off[o] * esize(v.dtype);
-    v.sx = (int32_t)st[0];
-    v.sy = (int32_t)st[1];
-    v.sz = (int32_t)st[2];
-    v.ori = o;
+    apply_copy(v, (forced >= 0 && forced <= 2) ? forced : best_copy(c.r));
 }
 
 int64_t vr_volume_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t brick_edge,
@@ -515,7 +508,8 @@ static bool tuning_valid(const vr_tuning &t) {
     // the LDS-staged kernel is compiled for 256-thread workgroups
     bool slab_shape = t.path != 2 || t.waves_per_group == 4;
     bool copy = t.copy >= -1 && t.copy <= 2;
-    return shape && waves && unroll && pg && path && lds && slab && slab_shape && copy;
+    bool order = t.order == 0 || t.order == 1;
+    return shape && waves && unroll && pg && path && lds && slab && slab_shape && copy && order;
 }
 
 int vr_set_tuning(vr_ctx *ctx, const vr_tuning *t) {

@@ -59,6 +59,32 @@ __host__ __device__ inline void copy_pitches(const VolDev &v, int c, int64_t &pf
     ps = n[(c + 2) % 3] + 2;
 }
 
+// Point v (describing copy 0 of a layout) at copy o: base pointer, strides
+// and orientation.  No-op for layouts without copies.
+__host__ __device__ inline void apply_copy(VolDev &v, int o) {
+    if (v.orients < 3 || o <= 0 || o > 2) return;
+    int64_t pf, pm, ps;
+    copy_pitches(v, o, pf, pm, ps);
+    int64_t st[3];
+    st[o] = 1;
+    st[(o + 1) % 3] = pf;
+    st[(o + 2) % 3] = pf * pm;
+    v.data = (const char *)v.data + v.copy_off[o] * (v.dtype == VR_F32 ? 4 : 2);
+    v.sx = (int32_t)st[0];
+    v.sy = (int32_t)st[1];
+    v.sz = (int32_t)st[2];
+    v.ori = o;
+}
+
+// The copy whose fastest axis runs along the image rows (largest |r_a|): a
+// ray packet spreads mostly along r, so its lanes then share cache lines.
+__host__ __device__ inline int best_copy(const double r[3]) {
+    int o = 0;
+    if (fabs(r[1]) > fabs(r[o])) o = 1;
+    if (fabs(r[2]) > fabs(r[o])) o = 2;
+    return o;
+}
+
 struct LutDev {
     const float4 *rgba;   // n entries, straight RGBA
     int32_t n;
@@ -248,6 +274,14 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
     uint32_t full = per * X;
     if (bid >= full) return bid;
     return (bid % X) * per + bid / X;
+}
+
+// Logical tile of hardware workgroup bid under a tile order (a bijection):
+//  0: each XCD takes one contiguous band of tiles (XCD-local L2 reuse);
+//  1: hardware order: neighbouring tiles run on different XCDs, so the work
+//     of a view whose volume covers only part of the frame spreads evenly.
+__device__ __forceinline__ uint32_t tile_order(uint32_t bid, uint32_t nblocks, int order) {
+    return order == 1 ? bid : xcd_remap(bid, nblocks);
 }
 
 }  // namespace vr

@@ -23,17 +23,20 @@ struct vr_ctx {
     vr_camera cam{};
     vr::CamDev camd{};
     // launch shape
-    vr_tuning tune{16, 4, 4, 1, 4, 0, 48, 16, -1};
+    vr_tuning tune{16, 4, 4, 2, 4, 0, 48, 16, -1, 1};
     // pinned staging for small device tables, and the event of its last copy
     void *stage = nullptr;
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr;
     bool stage_pending = false;
-    // batch graph cache
+    // batch graph cache: the captured (queue reset + persistent kernel) pair
+    // and the launch arguments it was captured with
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
     std::vector<int64_t> graph_key;
-    void *graph_stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int32_t cus = 256;    // compute units of the device
+    int32_t graph_captures = 0;
 };
 
 int vr_fail(const vr_ctx *ctx, int code, const char *fmt, ...);
@@ -47,3 +50,5 @@ void *vr_stage(vr_ctx *ctx, size_t bytes);
 // Copy the first `bytes` of the staging area to dst on stream s and record
 // the copy's completion.
 hipError_t vr_stage_copy(vr_ctx *ctx, void *dst, size_t bytes, hipStream_t s);
+
+int64_t vr_align256(int64_t x);

@@ -24,6 +24,7 @@ struct MarchArgs {
     int32_t waves;                // packets per workgroup (stacked vertically)
     int32_t groups_x;             // workgroups per tile row
     int32_t unroll;               // samples per inner iteration (direct path, one-brick layouts)
+    int32_t order;                // tile order (see tile_order)
 };
 
 // K0: transcode planes [z0, z1) of a float32 (z1-z0, ny, nx) source block
@@ -69,17 +70,17 @@ struct BackArgs {
 };
 hipError_t launch_backward(const BackArgs &a, hipStream_t s);
 
-// K6: persistent batch.
+// K6: persistent batch.  Work items are bw x bh pixel bundles of any view.
 struct ViewDev {
     CamDev cam;
     void *out;
     int32_t lut_index;
-    int32_t tiles_x;      // packet-group tiles across the view
+    int32_t tiles_x;      // bundles across the view
     int32_t tile_begin;   // first work item of the view
-    int32_t pad;
+    int32_t ori;          // orientation copy the view reads
 };
 struct BatchArgs {
-    VolDev vol;
+    VolDev vol;           // copy 0 of a one-brick layout
     const ViewDev *views;
     int32_t n_views;
     int32_t total_items;
@@ -89,11 +90,12 @@ struct BatchArgs {
     double step;
     float thr;
     int32_t ert;
-    int32_t mode, filter;
-    uint32_t *queue;      // work-queue counter (reset by the launcher each call)
-    int32_t packet_w, packet_h, waves;
+    int32_t trans;
+    uint32_t *queue;      // work-queue counter (zeroed by a kernel before each launch)
+    int32_t bw, bh;       // bundle
+    int32_t cap, lmax;    // LDS box budget (floats), thickest slab
 };
-hipError_t launch_batch(const BatchArgs &a, int32_t groups, hipStream_t s);
+hipError_t launch_batch(const BatchArgs &a, int32_t mode, int32_t filter, int32_t groups, hipStream_t s);
 hipError_t launch_reset_u32(uint32_t *p, int32_t n, hipStream_t s);
 
 }  // namespace vr

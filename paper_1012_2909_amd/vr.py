@@ -48,7 +48,8 @@ class View(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("packet_w", C.c_int32), ("packet_h", C.c_int32), ("waves_per_group", C.c_int32),
                 ("unroll", C.c_int32), ("persistent_groups", C.c_int32), ("path", C.c_int32),
-                ("lds_kib", C.c_int32), ("slab_max", C.c_int32), ("copy", C.c_int32)]
+                ("lds_kib", C.c_int32), ("slab_max", C.c_int32), ("copy", C.c_int32),
+                ("order", C.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point
@@ -80,6 +81,9 @@ SIGNATURES = [
     ("vr_batch_workspace_bytes", I64, [P, C.POINTER(View), I32]),
     ("vr_render_batch", C.c_int, [P, C.POINTER(RenderParams), C.POINTER(View), I32, P, I32, I32,
                                   F32, F32, P, I64, I32, P]),
+    ("vr_batch_graph_captures", C.c_int, [P]),
+    ("vr_autotune_batch", C.c_int, [P, C.POINTER(RenderParams), C.POINTER(View), I32, P, I32, I32, F32, F32,
+                                    P, I64, C.c_char_p, P]),
     ("vr_get_tuning", C.c_int, [P, C.POINTER(Tuning)]),
     ("vr_set_tuning", C.c_int, [P, C.POINTER(Tuning)]),
     ("vr_autotune", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, C.c_char_p, P]),
@@ -347,3 +351,79 @@ class Renderer:
         out = self.composite_bricks(parts, order, mode)
         self._keep = pool
         return out
+
+    # ---- batches and tuning ----------------------------------------------------
+    def _views(self, cams, outs, lut_index):
+        arr = (View * len(cams))()
+        for i, (c, o) in enumerate(zip(cams, outs)):
+            arr[i].cam = camera_struct(c)
+            arr[i].lut_index = int(lut_index[i])
+            arr[i].out = o.data_ptr()
+        return arr
+
+    def render_batch(self, cams, luts=None, lut_index=None, mode="composite", filt="trilinear", step=0.5, ert=0.99,
+                     trans="auto", outs=None, use_graph=False, workspace=None, stream=None):
+        """Render many views in one persistent launch.  luts: (n_luts, n, 4)
+        float32 cuda tensor (all over the range given to set_lut_range) or a
+        list of synth.Lut; returns the list of output tensors."""
+        p = params_struct(mode, filt, step, ert, trans)
+        n = len(cams)
+        if outs is None:
+            outs = [torch.empty((c.tile[3], c.tile[2], 4) if mode == "composite" else (c.tile[3], c.tile[2]),
+                                dtype=torch.float32, device=self.device) for c in cams]
+        if luts is None:
+            luts_t, vmin, vmax = self.lut.unsqueeze(0), *self.lut_range
+        elif isinstance(luts, tuple) and len(luts) == 3 and torch.is_tensor(luts[0]):
+            luts_t, vmin, vmax = luts
+        else:
+            luts_t, vmin, vmax = self.stack_luts(luts)
+        if lut_index is None:
+            lut_index = list(range(n)) if luts_t.shape[0] == n else [0] * n
+        views = self._views(cams, outs, lut_index)
+        need = int(self._check(lib().vr_batch_workspace_bytes(self.ctx, views, n)))
+        if workspace is None:
+            workspace = getattr(self, "_batch_ws", None)   # reused: graphs replay on the same workspace
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1 << 16), dtype=torch.uint8, device=self.device)
+            self._batch_ws = workspace
+        self._batch_keep = (luts_t, workspace, outs)
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+        self._check(lib().vr_render_batch(self.ctx, C.byref(p), views, n, _ptr(luts_t), int(luts_t.shape[0]),
+                                          int(luts_t.shape[1]), float(vmin), float(vmax), _ptr(workspace),
+                                          workspace.numel(), 1 if use_graph else 0, s))
+        return outs
+
+    def stack_luts(self, luts):
+        """(tensor (n_luts, n, 4) on the device, vmin, vmax) from a list of synth.Lut."""
+        t = torch.stack([torch.from_numpy(l.table) for l in luts]).to(self.device).contiguous()
+        return t, float(luts[0].vmin), float(luts[0].vmax)
+
+    def graph_captures(self):
+        return int(lib().vr_batch_graph_captures(self.ctx))
+
+    def autotune(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, cache_path=None):
+        p = params_struct(mode, filt, step, ert)
+        w, h = self.cam.tile[2], self.cam.tile[3]
+        out = torch.empty((h, w, 4) if mode == "composite" else (h, w), dtype=torch.float32, device=self.device)
+        cp = cache_path.encode() if cache_path else None
+        self._check(lib().vr_autotune(self.ctx, C.byref(p), _ptr(out), None, 0, cp, _stream()))
+        return self.get_tuning()
+
+    def autotune_batch(self, cams, luts, lut_index=None, mode="composite", filt="trilinear", step=0.5, ert=0.99,
+                       cache_path=None):
+        p = params_struct(mode, filt, step, ert)
+        n = len(cams)
+        outs = [torch.empty((c.tile[3], c.tile[2], 4) if mode == "composite" else (c.tile[3], c.tile[2]),
+                            dtype=torch.float32, device=self.device) for c in cams]
+        luts_t = torch.stack([torch.from_numpy(l.table) for l in luts]).to(self.device).contiguous()
+        if lut_index is None:
+            lut_index = list(range(n))
+        views = self._views(cams, outs, lut_index)
+        need = int(self._check(lib().vr_batch_workspace_bytes(self.ctx, views, n)))
+        ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        cp = cache_path.encode() if cache_path else None
+        self._check(lib().vr_autotune_batch(self.ctx, C.byref(p), views, n, _ptr(luts_t), int(luts_t.shape[0]),
+                                            int(luts_t.shape[1]), float(luts[0].vmin), float(luts[0].vmax),
+                                            _ptr(ws), ws.numel(), cp, _stream()))
+        torch.cuda.synchronize()
+        return self.get_tuning()

@@ -124,9 +124,9 @@ def test_argument_errors(hctx):
     assert L.vr_set_camera(h, C.byref(_cam(vr, eye=(float("nan"), 0.0, 0.0)))) == vr.EINVAL
     assert L.vr_set_camera(h, C.byref(_cam(vr))) == vr.OK
     # tuning
-    t = vr.Tuning(7, 9, 4, 1, 4, 0, 48, 16, -1)
+    t = vr.Tuning(7, 9, 4, 1, 4, 0, 48, 16, -1, 1)
     assert L.vr_set_tuning(h, C.byref(t)) == vr.EINVAL
-    t = vr.Tuning(16, 4, 2, 2, 4, 1, 32, 8, 2)
+    t = vr.Tuning(16, 4, 2, 2, 4, 1, 32, 8, 2, 0)
     assert L.vr_set_tuning(h, C.byref(t)) == vr.OK
     t2 = vr.Tuning()
     assert L.vr_get_tuning(h, C.byref(t2)) == vr.OK and (t2.packet_w, t2.waves_per_group) == (16, 2)

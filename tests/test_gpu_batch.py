@@ -1,0 +1,136 @@
+"""GPU tests of the batched renderer (one persistent launch over many uneven
+views, optionally replayed from a HIP graph) and of the autotuner.  A batch
+must reproduce, bit for bit, the images of the same views rendered one by one
+(the arithmetic per pixel is the same), and those images are checked against
+the FP64 oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1012_2909_amd import synth
+from tests.gpu_util import TOL_COMPOSITE, assert_accept, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1012_2909_amd import vr
+    r = vr.Renderer(0)
+    yield r
+    r.close()
+
+
+SHAPE = (80, 56, 64)
+
+
+@pytest.fixture(scope="module")
+def cube():
+    return synth.make_cube(synth.CubeSpec(SHAPE, 16, seed=44, fwhm_z=(4.0, 24.0)))
+
+
+def _views(seed, n, wr=(17, 260), hr=(9, 150)):
+    cams, luts = synth.batch_views(SHAPE, seed, n_views=n, w_range=wr, h_range=hr)
+    return cams, luts
+
+
+def _one_by_one(R, cams, luts, mode="composite"):
+    out = []
+    for c, l in zip(cams, luts):
+        R.set_lut(l)
+        R.set_camera(c)
+        out.append(R.render(mode=mode).cpu().numpy())
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("mode", ["composite", "mip"])
+def test_batch_equals_single_views(R, cube, storage, mode):
+    log(f"case: batch storage={storage} mode={mode}")
+    R.load_volume(torch.from_numpy(cube), storage=storage)
+    cams, luts = _views(7, 9)
+    got = R.render_batch(cams, luts, mode=mode)
+    torch.cuda.synchronize()
+    ref = _one_by_one(R, cams, luts, mode)
+    for i, (g, r) in enumerate(zip(got, ref)):
+        assert np.array_equal(g.cpu().numpy(), r), f"view {i} differs"
+    # two of the views against the oracle
+    vol = cube if storage == "f32" else torch.from_numpy(cube).half().float().numpy()
+    for i in (0, 5):
+        res = oracle.render(vol, luts[i], cams[i], mode=mode, eps_stop=2e-5)
+        if mode == "composite":
+            assert_accept(ref[i], res, TOL_COMPOSITE, what=f"batch view {i}")
+        else:
+            assert_accept(ref[i], res, 1e-6, rel=1e-6, what=f"batch view {i} MIP")
+
+
+def test_graph_replays_match_eager(R, cube):
+    """Capture once, replay with new cameras and outputs (same sizes), with
+    eager work in between; every replay equals the eager images."""
+    R.load_volume(torch.from_numpy(cube))
+    cams, luts = _views(11, 6)
+    packed = R.stack_luts(luts)           # one table tensor for every replay
+    s = torch.cuda.Stream()
+    n0 = R.graph_captures()
+    for rep in range(4):
+        # new camera positions with the same viewport sizes
+        moved = [synth.orbit_camera(SHAPE, seed=100 * rep + i, w=c.full_w, h=c.full_h) for i, c in enumerate(cams)]
+        with torch.cuda.stream(s):
+            got = R.render_batch(moved, packed, use_graph=True, stream=s)
+        s.synchronize()
+        eager = _one_by_one(R, moved, luts)          # eager work between replays
+        torch.cuda.synchronize()
+        for i, (g, e) in enumerate(zip(got, eager)):
+            assert np.array_equal(g.cpu().numpy(), e), f"replay {rep} view {i}"
+    assert R.graph_captures() == n0 + 1
+    # a different batch shape captures again
+    cams2, luts2 = _views(12, 3)
+    with torch.cuda.stream(s):
+        R.render_batch(cams2, luts2, use_graph=True, stream=s)
+    s.synchronize()
+    assert R.graph_captures() == n0 + 2
+
+
+def test_five_by_five_wall_in_one_batch(R, cube):
+    """The 25 panels of a tiled frame rendered as one batch stitch into the
+    full-frame render."""
+    R.load_volume(torch.from_numpy(cube))
+    lut = synth.lut_ramp()
+    cam = synth.orbit_camera(SHAPE, seed=3, w=5 * 40, h=5 * 24)
+    R.set_lut(lut)
+    R.set_camera(cam)
+    full = R.render().cpu().numpy()
+    tiles = synth.tiles_5x5(cam, 40, 24)
+    outs = R.render_batch(tiles, [lut])
+    torch.cuda.synchronize()
+    st = np.zeros_like(full)
+    for t, o in zip(tiles, outs):
+        x0, y0, w, h = t.tile
+        st[y0:y0 + h, x0:x0 + w] = o.cpu().numpy()
+    assert np.array_equal(st, full)
+
+
+def test_autotune_and_cache(R, cube, tmp_path):
+    R.load_volume(torch.from_numpy(cube))
+    R.set_lut(synth.lut_ramp())
+    R.set_camera(synth.orbit_camera(SHAPE, seed=1, w=300, h=200))
+    path = str(tmp_path / "tune.json")
+    t1 = R.autotune(cache_path=path)
+    data = json.load(open(path))
+    assert len(data) == 1 and list(data.values())[0][5] in (1, 2)
+    R.set_tuning(path=1, packet_w=8, packet_h=8)
+    t2 = R.autotune(cache_path=path)           # cache hit restores the tuned shape
+    assert t2 == t1
+    cams, luts = _views(5, 5)
+    tb = R.autotune_batch(cams, luts, cache_path=path)
+    assert len(json.load(open(path))) == 2 and tb["path"] == 2
+    # the tuned shapes still render correctly
+    got = R.render_batch(cams, luts)
+    torch.cuda.synchronize()
+    ref = _one_by_one(R, cams, luts)
+    for g, r in zip(got, ref):
+        assert np.array_equal(g.cpu().numpy(), r)

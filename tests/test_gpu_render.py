@@ -134,7 +134,8 @@ TUNES = [dict(path=1), dict(path=1, packet_w=8, packet_h=8, waves_per_group=8),
          dict(path=1, unroll=4, packet_w=64, packet_h=1),
          dict(path=1, copy=0), dict(path=1, copy=1), dict(path=1, copy=2, unroll=2),
          dict(path=2, copy=0), dict(path=2, copy=1), dict(path=2, copy=2, lds_kib=96),
-         dict(path=2, copy=1, lds_kib=8, slab_max=2)]
+         dict(path=2, copy=1, lds_kib=8, slab_max=2), dict(path=1, order=0), dict(path=2, order=0),
+         dict(path=1, order=1, unroll=4)]
 
 
 @pytest.mark.parametrize("mode,filt", [("composite", "trilinear"), ("mip", "nearest"), ("mip", "trilinear")])
