@@ -6,8 +6,9 @@ seeded orbit angles, step 0.5 voxel.  One step renders one frame (the next
 angle) in both modes: composite (256-entry grey ramp over [-3, 10], early
 stop at alpha 0.99) and trilinear maximum-intensity projection.  Inputs are
 resident in HBM before the timed region; the volume layout (transcode) is
-timed separately.  Launch shapes come from the library's autotuner (one
-search per mode on the first angle).  Prints one JSON line.
+timed separately.  Launch shapes are the library's defaults: the path (LDS-staged
+voxel boxes for MIP, direct gathers for the early-stopping composite) and
+the LDS budget are chosen per view.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 16] [--warmup 2] [--no-cpu]
 """
@@ -55,7 +56,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work of the oracle sample")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shapes")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune one launch shape per mode on the first angle (default: the library's automatic "
+                         "per-view choice of path and LDS budget)")
     ap.add_argument("--tune-cache", default="/tmp/vrcube_tune.json", help="autotuner cache file ('' for none)")
     ap.add_argument("--measure-cache", default="/tmp/vrcube_bench_measure.json",
                     help="cache of the per-angle sample counts and touched blocks ('' for none)")
@@ -116,7 +119,7 @@ def main():
     tunes = {}
     R.set_camera(cams[0])
     for name, kw in modes.items():
-        if args.no_tune:
+        if not args.tune:
             tunes[name] = R.get_tuning()
         else:
             tunes[name] = R.autotune(mode=kw["mode"], filt=kw["filt"], step=step, ert=kw["ert"],

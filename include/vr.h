@@ -124,16 +124,18 @@ typedef struct {
  * 64-lane wave per packet_w x packet_h packet. */
 typedef struct {
     int32_t packet_w, packet_h;   /* pixels per wavefront packet: 8x8, 16x4, 32x2, 64x1, 4x16 */
-    int32_t waves_per_group;      /* 1, 2, 4 (LDS-staged path: 4 only), 8 (direct path only) */
+    int32_t waves_per_group;      /* 1, 2, 4, 8 (LDS-staged path: 4 or 8) */
     int32_t unroll;               /* direct path on one-brick layouts: samples per inner iteration, 1, 2, 4 */
     int32_t persistent_groups;    /* batched launch: workgroups per CU, 1..32 */
     int32_t path;                 /* 0 auto, 1 direct gathers, 2 LDS-staged voxel boxes (one-brick layouts) */
-    int32_t lds_kib;              /* LDS-staged path: voxel-box budget per workgroup, 8..144 KiB */
+    int32_t lds_kib;              /* LDS-staged path: voxel-box budget per workgroup, 8..144 KiB;
+                                     0 = per view: 144 KiB for views oblique to all three axes, else 64 */
     int32_t slab_max;             /* LDS-staged path: thickest slab tried, 1..64 voxels */
     int32_t copy;                 /* layouts with 3 orientation copies: -1 auto (fastest axis along the
                                      image rows), 0/1/2 force the x/y/z-fastest copy */
     int32_t order;                /* tile order: 0 one contiguous band of tiles per XCD (L2 reuse),
-                                     1 hardware order (work spread evenly over the XCDs) */
+                                     1 hardware order (work spread evenly over the XCDs),
+                                     2 4x4-tile blocks per XCD, blocks dealt over the XCDs in turn */
 } vr_tuning;
 
 /* ---- context ---------------------------------------------------------- */

@@ -70,9 +70,10 @@ struct Walker {
 };
 
 // Pixel of this lane for the packet layout; false if outside the tile.
-__device__ __forceinline__ bool lane_pixel(const MarchArgs &A, uint32_t group, int &px, int &py) {
+__device__ __forceinline__ bool lane_pixel(const MarchArgs &A, int &px, int &py) {
     int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int gx = group % A.groups_x, gy = group / A.groups_x;
+    int32_t gx, gy;
+    tile_xy(blockIdx.x, gridDim.x, A.groups_x, (int32_t)(gridDim.x / (uint32_t)A.groups_x), A.order, gx, gy);
     px = gx * A.packet_w + lane % A.packet_w;
     py = (gy * A.waves + wave) * A.packet_h + lane / A.packet_w;
     return px < A.cam.tile_w && py < A.cam.tile_h;
@@ -82,8 +83,7 @@ template <typename S, int MODE, int FILTER, bool SINGLE>
 __global__ __launch_bounds__(512) void k_march(MarchArgs A) {
     __shared__ float4 lut[1024];
     int px, py;
-    uint32_t group = tile_order(blockIdx.x, gridDim.x, A.order);
-    const bool valid = lane_pixel(A, group, px, py);
+    const bool valid = lane_pixel(A, px, py);
     int64_t pix = (int64_t)py * A.cam.tile_w + px;
 
     Ray r{};
@@ -141,8 +141,7 @@ template <typename S, int MODE, int FILTER, int U>
 __global__ __launch_bounds__(256) void k_march_u(MarchArgs A) {
     __shared__ float4 lut[1024];
     int px, py;
-    uint32_t group = tile_order(blockIdx.x, gridDim.x, A.order);
-    const bool valid = lane_pixel(A, group, px, py);
+    const bool valid = lane_pixel(A, px, py);
     const int64_t pix = (int64_t)py * A.cam.tile_w + px;
     const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
     Ray r{};
@@ -212,7 +211,7 @@ __global__ __launch_bounds__(256) void k_touch(MarchArgs A, int32_t mode, int32_
     for (int i = threadIdx.x; i < A.lut.n; i += blockDim.x) lut[i] = A.lut.rgba[i];
     __syncthreads();
     int px, py;
-    if (!lane_pixel(A, blockIdx.x, px, py)) return;
+    if (!lane_pixel(A, px, py)) return;
     Ray r;
     make_ray(A.cam, A.vol, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
     int64_t Q[3], D[3];

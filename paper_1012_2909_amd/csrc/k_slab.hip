@@ -28,39 +28,33 @@ struct SlabArgs {
     int32_t lmax;         // largest slab thickness tried
 };
 
-// Sample from the LDS box at element offset off; lsx/lsy/lsz are the box
-// strides of x, y and z (the box keeps the axis order of the copy it came
-// from).
-template <int FILTER>
-__device__ __forceinline__ float lsample(const float *box, uint32_t off, uint32_t lsx, uint32_t lsy, uint32_t lsz,
-                                         float fx, float fy, float fz) {
-    if (FILTER == VR_NEAREST) return box[off];
-    const float *p = box + off;
-    float c000 = p[0], c100 = p[lsx], c010 = p[lsy], c110 = p[lsy + lsx];
-    const float *q = p + lsz;
-    float c001 = q[0], c101 = q[lsx], c011 = q[lsy], c111 = q[lsy + lsx];
-    float x00 = fmaf(fx, c100 - c000, c000), x10 = fmaf(fx, c110 - c010, c010);
-    float x01 = fmaf(fx, c101 - c001, c001), x11 = fmaf(fx, c111 - c011, c011);
-    float y0 = fmaf(fy, x10 - x00, x00), y1 = fmaf(fy, x11 - x01, x01);
-    return fmaf(fz, y1 - y0, y0);
+// A 16-byte chunk of storage, already in registers -> floats in LDS.
+template <typename S> __device__ __forceinline__ void put_raw(float *dst, uint4 v);
+template <> __device__ __forceinline__ void put_raw<float>(float *dst, uint4 v) { *(uint4 *)dst = v; }
+template <> __device__ __forceinline__ void put_raw<_Float16>(float *dst, uint4 v) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 a = __builtin_bit_cast(h2, v.x), b = __builtin_bit_cast(h2, v.y);
+    const h2 c = __builtin_bit_cast(h2, v.z), d = __builtin_bit_cast(h2, v.w);
+    *(float4 *)dst = make_float4((float)a[0], (float)a[1], (float)b[0], (float)b[1]);
+    *(float4 *)(dst + 4) = make_float4((float)c[0], (float)c[1], (float)d[0], (float)d[1]);
 }
-
-// 16 bytes of storage -> floats in LDS.
-__device__ __forceinline__ void put_chunk(float *dst, const float *src) {
-    *(float4 *)dst = *(const float4 *)src;
-}
-__device__ __forceinline__ void put_chunk(float *dst, const _Float16 *src) {
-    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-    h8 v = *(const h8 *)src;
-    *(float4 *)dst = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-    *(float4 *)(dst + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
-}
-__device__ __forceinline__ void put_chunk(float *dst, const bf16_t *src) {
-    uint4 v = *(const uint4 *)src;
+template <> __device__ __forceinline__ void put_raw<bf16_t>(float *dst, uint4 v) {
     *(float4 *)dst = make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
                                  __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
     *(float4 *)(dst + 4) = make_float4(__uint_as_float(v.z << 16), __uint_as_float(v.z & 0xffff0000u),
                                        __uint_as_float(v.w << 16), __uint_as_float(v.w & 0xffff0000u));
+}
+
+// Largest number of 16-byte chunks one thread stages per slab (all loads of
+// a slab are in flight together; the slab thickness is chosen to fit).
+constexpr int kMaxPasses = 16;
+
+// Exact quotient of small non-negative integers, n <= 1024 and 1 <= d <=
+// 1024, in FP32: (n + 1/2)/d lies at least 1/(2d) >= 2^-11 from any integer,
+// while the rounding of the reciprocal (1 ulp) and of the product moves it by
+// under n * 2^-22 <= 2^-12.
+__device__ __forceinline__ int32_t sdiv(int32_t n, int32_t d) {
+    return (int32_t)(((float)n + 0.5f) * __builtin_amdgcn_rcpf((float)d));
 }
 
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
@@ -84,12 +78,6 @@ __device__ __forceinline__ void wg_minmax(int32_t &mn, int32_t &mx, int32_t *red
     mn = red[0];
     mx = red[8];
     for (int i = 1; i < nw; ++i) { mn = min(mn, red[i]); mx = max(mx, red[8 + i]); }
-}
-
-// Floor division for possibly negative numerators (positive divisor).
-__device__ __forceinline__ int32_t fdiv(int32_t a, int32_t b) {
-    int32_t q = a / b;
-    return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
 // Uniform description of the bundle's frustum: per corner ray the lateral
@@ -151,7 +139,12 @@ template <int MODE>
 __device__ __forceinline__ bool consume(LaneState &L, const MarchArgs &A, const float4 *lut, int64_t pix,
                                         int64_t npix, float s) {
     if (MODE == VR_MIP) {
-        L.m = fmaxf(L.m, s);
+        // max(m, s) as the bare instruction: both are results of FP
+        // arithmetic (or -inf), so the quieting the compiler would add for
+        // fmaxf is not needed
+        float r;
+        asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(s), "v"(L.m));
+        L.m = r;
         return true;
     }
     if (A.ckpt && (L.k & 63) == 0 && (L.k >> 6) < A.ckpt_segs) A.ckpt[(int64_t)(L.k >> 6) * npix + pix] = L.T;
@@ -164,90 +157,260 @@ __device__ __forceinline__ bool consume(LaneState &L, const MarchArgs &A, const 
     return !(A.ert && L.T <= A.thr);
 }
 
-// The slab march for slab axis W (0, 1, 2 = x, y, z) over the copy whose
-// fastest axis is ORI.
-template <typename S, int MODE, int FILTER, int W, int ORI>
+// Box of the slab [lo, lo + L) (corner index along W) in the copy's axis
+// order: chunk-aligned origin fp0 along the fastest axis and the LDS
+// dimensions; false if it is empty or too thin for the 2x2x2 footprint.
+template <int W, int ORI, int EPC, int FILTER>
+__device__ __forceinline__ bool slab_dims(const Frustum &F, int32_t lo, int32_t L, int32_t b0[3], int32_t &fp0,
+                                          int32_t &Df, int32_t &Dm, int32_t &Ds) {
+    constexpr int U = W == 0 ? 1 : 0, VV = W == 2 ? 1 : 2;
+    constexpr int AF = ORI, AM = (ORI + 1) % 3, AS = (ORI + 2) % 3;
+    int32_t lu, hu, lv, hv, lw, hw;
+    slab_box(F, lo, L, lu, hu, lv, hv, lw, hw);
+    int32_t b1[3];
+    b0[W] = lw; b1[W] = hw; b0[U] = lu; b1[U] = hu; b0[VV] = lv; b1[VV] = hv;
+    box_dims<EPC>(b0[AF], b1[AF], b0[AM], b1[AM], b0[AS], b1[AS], fp0, Df, Dm, Ds);
+    if (Df <= 0 || Dm <= 0 || Ds <= 0) return false;
+    return FILTER == VR_NEAREST || (Df >= 2 && Dm >= 2 && Ds >= 2);
+}
+
+// Samples of one lane inside the current slab, read from the LDS box.  The
+// slab test and the end of the ray are one 64-bit comparison of the
+// position along W with lim.  The box is in the copy's axis order: element
+// strides 1, esm, ess for the fastest, middle and slowest axis (bM, bS in
+// bytes), base the element offset of corner index (0,0,0); every box read is
+// kept inside [0, maxoff] + the footprint.
+template <int MODE, int FILTER, int W, int ORI, int SW>
+__device__ __forceinline__ void lds_samples(LaneState &ls, const MarchArgs &A, const float4 *lut, int64_t pix,
+                                            int64_t npix, const char *lds, int32_t esm, int32_t ess, int32_t base,
+                                            uint32_t maxoff, uint32_t bM, uint32_t bS, int64_t lim) {
+    int64_t q0 = ls.Q[0], q1 = ls.Q[1], q2 = ls.Q[2];
+    const int64_t d0 = ls.D[0], d1 = ls.D[1], d2 = ls.D[2];
+    int32_t k = ls.k;
+    auto inside = [&](int64_t qw) { return SW > 0 ? qw < lim : qw >= lim; };
+    if (inside(W == 0 ? q0 : (W == 1 ? q1 : q2))) do {
+        // element offset: the fastest axis has stride 1, the other two go
+        // through 24-bit multiplies; then bytes
+        const int32_t i0 = fix_int(q0), i1 = fix_int(q1), i2 = fix_int(q2);
+        const int32_t ia = ORI == 0 ? i0 : (ORI == 1 ? i1 : i2);
+        const int32_t ib = ORI == 0 ? i1 : (ORI == 1 ? i2 : i0);
+        const int32_t ic = ORI == 0 ? i2 : (ORI == 1 ? i0 : i1);
+        const int32_t off = ia + __mul24(ib, esm) + __mul24(ic, ess) + base;
+        const uint32_t o = min((uint32_t)off, maxoff) << 2;
+        float s;
+        if (FILTER == VR_NEAREST) {
+            s = *(const float *)(lds + o);
+        } else {
+            const float fx = fix_frac(q0), fy = fix_frac(q1), fz = fix_frac(q2);
+            // pairs along the fastest axis at the four (middle, slowest) corners
+            const float *pa = (const float *)(lds + o), *pb = (const float *)(lds + o + bM);
+            const float *pc = (const float *)(lds + o + bS), *pd = (const float *)(lds + o + bM + bS);
+            const float a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+            const float c0 = pc[0], c1 = pc[1], e0 = pd[0], e1 = pd[1];
+            float c000, c100, c010, c110, c001, c101, c011, c111;
+            if (ORI == 0) {        // fastest x, then y, z
+                c000 = a0; c100 = a1; c010 = b0; c110 = b1; c001 = c0; c101 = c1; c011 = e0; c111 = e1;
+            } else if (ORI == 1) { // fastest y, then z, x
+                c000 = a0; c010 = a1; c001 = b0; c011 = b1; c100 = c0; c110 = c1; c101 = e0; c111 = e1;
+            } else {               // fastest z, then x, y
+                c000 = a0; c001 = a1; c100 = b0; c101 = b1; c010 = c0; c011 = c1; c110 = e0; c111 = e1;
+            }
+            const float x00 = fmaf(fx, c100 - c000, c000), x10 = fmaf(fx, c110 - c010, c010);
+            const float x01 = fmaf(fx, c101 - c001, c001), x11 = fmaf(fx, c111 - c011, c011);
+            const float y0 = fmaf(fy, x10 - x00, x00), y1 = fmaf(fy, x11 - x01, x01);
+            s = fmaf(fz, y1 - y0, y0);
+        }
+        q0 += d0; q1 += d1; q2 += d2;
+        ls.k = k;
+        const bool go = consume<MODE>(ls, A, lut, pix, npix, s);
+        ++k;
+        if (!go) { ls.stopped = true; break; }
+    } while (inside(W == 0 ? q0 : (W == 1 ? q1 : q2)));
+    ls.k = k;
+    ls.Q[0] = q0; ls.Q[1] = q1; ls.Q[2] = q2;
+}
+
+// The same samples gathered straight from the volume (slabs whose box does
+// not fit the LDS budget).
+template <typename S, int MODE, int FILTER, int W, int SW>
+__device__ __forceinline__ void gather_samples(LaneState &ls, const MarchArgs &A, const float4 *lut, int64_t pix,
+                                               int64_t npix, int64_t lim) {
+    for (;;) {
+        const int64_t qw = ls.Q[W];
+        if (SW > 0 ? !(qw < lim) : !(qw >= lim)) break;
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        if (FILTER == VR_TRILINEAR) { fx = fix_frac(ls.Q[0]); fy = fix_frac(ls.Q[1]); fz = fix_frac(ls.Q[2]); }
+        const float s = gsample<S, FILTER>(A.vol, fix_int(ls.Q[0]), fix_int(ls.Q[1]), fix_int(ls.Q[2]), fx, fy, fz);
+        ls.Q[0] += ls.D[0]; ls.Q[1] += ls.D[1]; ls.Q[2] += ls.D[2];
+        const bool go = consume<MODE>(ls, A, lut, pix, npix, s);
+        ++ls.k;
+        if (!go) { ls.stopped = true; break; }
+    }
+}
+
+// One slab of the march: corner indices [lo, lo + L) along W, and its voxel
+// box (in the copy's axis order) if that is staged in LDS.
+struct SlabPlan {
+    int32_t lo, L, fp0, Df, Dm, Ds, b0[3];
+    bool lds;
+};
+
+// The thickest slab starting at corner index cur (in the march direction),
+// at most one thicker than the previous one and at most rem, whose box fits
+// the LDS budget; a slab of thickness 1 that does not fit is marched with
+// direct gathers.
+template <typename S, int W, int ORI, int FILTER, int SW>
+__device__ __forceinline__ SlabPlan plan_slab(const SlabArgs &SA, const Frustum &F, int32_t cur, int32_t Lprev,
+                                              int32_t rem, int nthr) {
+    constexpr int EPC = 16 / (int)sizeof(S);
+    SlabPlan sl;
+    auto fits = [&](int32_t Lt, SlabPlan &p) {
+        p.lo = SW > 0 ? cur : cur - Lt + 1;
+        p.L = Lt;
+        p.lds = slab_dims<W, ORI, EPC, FILTER>(F, p.lo, Lt, p.b0, p.fp0, p.Df, p.Dm, p.Ds) &&
+                (int64_t)p.Df * p.Dm * p.Ds <= SA.cap && p.Df / EPC <= nthr;
+        return p.lds;
+    };
+    int32_t Lt = min(min(Lprev, SA.lmax), rem);
+    if (fits(Lt, sl)) {
+        // one thicker if the box has room for another plane
+        const int64_t e = (int64_t)sl.Df * sl.Dm * sl.Ds;
+        SlabPlan g;
+        if (Lt < min(SA.lmax, rem) && e + e / Lt <= SA.cap && fits(Lt + 1, g)) sl = g;
+        return sl;
+    }
+    while (Lt > 1) {
+        Lt = Lt > 8 ? Lt - (Lt >> 2) : Lt - 1;
+        if (fits(Lt, sl)) break;
+    }
+    return sl;
+}
+
+// This thread's walk over the 16-byte chunks of a slab's box: rpp rows of
+// cpr chunks per pass; thread t < rpp*cpr takes chunk t mod cpr of row
+// t / cpr, then the same chunk rpp rows further on.  A round covers
+// kMaxPasses passes.
+template <typename S, int ORI>
+struct BoxWalk {
+    const S *gbase;
+    float *dst;
+    uint32_t goff, gA, gB;
+    int32_t mm, mstep, Dm, rpp, rows, row0, dstep;
+    bool on;
+
+    __device__ __forceinline__ void init(const SlabPlan &sl, const VolDev &V, float *box, int tid, int nthr) {
+        constexpr int AM = (ORI + 1) % 3, AS = (ORI + 2) % 3;
+        constexpr int EPC = 16 / (int)sizeof(S);
+        const uint32_t gstr[3] = {(uint32_t)V.sx, (uint32_t)V.sy, (uint32_t)V.sz};
+        // cpr <= nthr <= 512 and rows per pass <= 512 (checked when the slab
+        // was planned), so every quotient here is an exact sdiv
+        const int32_t cpr = sl.Df / EPC;
+        Dm = sl.Dm;
+        rows = sl.Dm * sl.Ds;
+        rpp = sdiv(nthr, cpr);
+        row0 = sdiv(tid, cpr);
+        const int32_t tx = tid - row0 * cpr;
+        on = row0 < rpp;
+        const int32_t Dq = min(Dm, 1024);                 // row0 < Dm whenever Dm > 1024
+        const int32_t sq = sdiv(row0, Dq);
+        mm = row0 - sq * Dq;
+        const int32_t sstep = sdiv(rpp, Dq);
+        mstep = rpp - sstep * Dq;
+        gbase = (const S *)V.data + ((size_t)(sl.b0[AS] + 1) * gstr[AS] + (size_t)(sl.b0[AM] + 1) * gstr[AM] +
+                                     (size_t)sl.fp0);
+        goff = (uint32_t)sq * gstr[AS] + (uint32_t)mm * gstr[AM] + (uint32_t)(tx * EPC);
+        gA = (uint32_t)sstep * gstr[AS] + (uint32_t)mstep * gstr[AM];
+        gB = gstr[AS] - (uint32_t)Dm * gstr[AM];
+        dst = box + (row0 * sl.Df + tx * EPC);
+        dstep = rpp * sl.Df;
+    }
+    // Issue the loads of the round whose first row is r0; nothing waits.
+    // Loads and stores are unconditional (a chunk past the box reloads the
+    // box's first chunk and is stored to the spare slot after the box), so
+    // that no branch splits the sequence and all loads stay in flight.
+    __device__ __forceinline__ void load(uint4 (&raw)[kMaxPasses], int32_t r0) {
+#pragma unroll
+        for (int p = 0; p < kMaxPasses; ++p) {
+            const bool ok = on && r0 + p * rpp < rows;
+            raw[p] = *(const uint4 *)(gbase + (ok ? goff : 0u));
+            goff += gA;
+            mm += mstep;
+            if (mm >= Dm) { mm -= Dm; goff += gB; }
+        }
+    }
+    __device__ __forceinline__ void store(const uint4 (&raw)[kMaxPasses], int32_t r0, float *spare) {
+#pragma unroll
+        for (int p = 0; p < kMaxPasses; ++p) {
+            const bool ok = on && r0 + p * rpp < rows;
+            put_raw<S>(ok ? dst : spare, raw[p]);
+            dst += dstep;
+        }
+    }
+};
+
+// The slab march for slab axis W (0, 1, 2 = x, y, z) and direction SW over
+// the copy whose fastest axis is ORI.  The slabs cover the corner-index range
+// [wlo, whi] of the bundle's regular lanes in order; each slab is as thick
+// as the LDS budget allows at that depth (a perspective bundle widens with
+// distance), at most lmax.  The box loads of the next slab are issued before
+// the current slab is sampled, so their latency hides behind the sampling.
+template <typename S, int MODE, int FILTER, int W, int ORI, int SW>
 __device__ __forceinline__ void run_slabs(const SlabArgs &SA, const Frustum &F, LaneState &ls, bool active,
-                                          int32_t L, int32_t sw, int32_t c, float *box, const float4 *lut,
-                                          int64_t pix, int64_t npix) {
+                                          int32_t wlo, int32_t whi, float *box, const float4 *lut, int64_t pix,
+                                          int64_t npix) {
     const MarchArgs &A = SA.m;
     const VolDev &V = A.vol;
-    constexpr int U = W == 0 ? 1 : 0, VV = W == 2 ? 1 : 2;
-    constexpr int AF = ORI, AM = (ORI + 1) % 3, AS = (ORI + 2) % 3;   // fastest, middle, slowest axis
-    constexpr int EPC = 16 / (int)sizeof(S);          // storage elements per 16-byte chunk
+    constexpr int AM = (ORI + 1) % 3, AS = (ORI + 2) % 3;   // middle and slowest axis
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int32_t max_iter = (F.Nw + 2) / L + 3;
-    const uint32_t gstr[3] = {(uint32_t)V.sx, (uint32_t)V.sy, (uint32_t)V.sz};
-    int32_t iter = 0;
-    while (__syncthreads_or(active) && iter++ < max_iter) {
-        const int32_t lo_w = c * L;
-        int32_t lu, hu, lv, hv, lw, hw;
-        slab_box(F, lo_w, L, lu, hu, lv, hv, lw, hw);
-        int32_t b0[3], b1[3];
-        b0[W] = lw; b1[W] = hw; b0[U] = lu; b1[U] = hu; b0[VV] = lv; b1[VV] = hv;
-        int32_t fp0, Df, Dm, Ds;
-        box_dims<EPC>(b0[AF], b1[AF], b0[AM], b1[AM], b0[AS], b1[AS], fp0, Df, Dm, Ds);
-        const bool empty = Df <= 0 || Dm <= 0 || Ds <= 0;
-        const bool fits = FILTER == VR_NEAREST || (Df >= 2 && Dm >= 2 && Ds >= 2);
-        const bool use_lds = !empty && fits && (int64_t)Df * Dm * Ds <= SA.cap;
-        if (use_lds) {
-            // chunks per row, lanes per row (power of two), rows per pass
-            const int32_t cpr = Df / EPC;
-            int32_t lpr = 1;
-            while (lpr < cpr && lpr < nthr) lpr <<= 1;
-            const int32_t rpp = nthr / lpr;
-            const int32_t tx = tid % lpr;
-            int32_t row = tid / lpr;
-            int32_t mm = row % Dm, ss = row / Dm;           // once per slab
-            const int32_t mstep = rpp % Dm, sstep = rpp / Dm;
-            const int32_t rows = Dm * Ds;
-            for (; row < rows; row += rpp) {
-                const S *src = (const S *)V.data + ((size_t)(b0[AS] + ss + 1) * gstr[AS] +
-                                                    (size_t)(b0[AM] + mm + 1) * gstr[AM] + (size_t)fp0);
-                float *dst = box + (size_t)row * Df;
-                for (int32_t cx = tx; cx < cpr; cx += lpr) put_chunk(dst + cx * EPC, src + cx * EPC);
-                mm += mstep;
-                ss += sstep;
-                if (mm >= Dm) { mm -= Dm; ++ss; }
+    // the position along W of the lane's last sample
+    const int64_t qlast = ls.Q[W] + (int64_t)(ls.n > 0 ? ls.n - 1 : 0) * ls.D[W];
+    auto remaining = [&](int32_t c) { return SW > 0 ? whi - c + 1 : c - wlo + 1; };
+    int32_t cur = SW > 0 ? wlo : whi;                 // first corner index not yet covered
+    uint4 raw[kMaxPasses];
+    BoxWalk<S, ORI> wk;
+    SlabPlan nxt = plan_slab<S, W, ORI, FILTER, SW>(SA, F, cur, SA.lmax, remaining(cur), nthr);
+    if (nxt.lds) {
+        wk.init(nxt, V, box, tid, nthr);
+        wk.load(raw, wk.row0);
+    }
+    while (__syncthreads_or(active)) {
+        if (remaining(cur) <= 0) break;
+        const SlabPlan sl = nxt;
+        if (sl.lds) {
+            float *spare = box + SA.cap;                  // 8 floats past the largest box
+            wk.store(raw, wk.row0, spare);
+            for (int32_t r0 = wk.row0 + wk.rpp * kMaxPasses; r0 < wk.rows; r0 += wk.rpp * kMaxPasses) {
+                wk.load(raw, r0);
+                wk.store(raw, r0, spare);
             }
             __syncthreads();
         }
-        if (active) {
-            // box strides of x, y, z and the box origin in padded index
-            uint32_t lstr[3];
-            lstr[AF] = 1;
-            lstr[AM] = (uint32_t)Df;
-            lstr[AS] = (uint32_t)Df * (uint32_t)Dm;
-            int32_t org[3], lim[3];
-            org[AF] = fp0 - 1; org[AM] = b0[AM]; org[AS] = b0[AS];
-            const int32_t t1 = FILTER == VR_TRILINEAR ? 1 : 0;
-            lim[AF] = Df - 1 - t1; lim[AM] = Dm - 1 - t1; lim[AS] = Ds - 1 - t1;
-            const int32_t wlast = lo_w + L - 1;
-            while (true) {
-                const int32_t iw = fix_int(ls.Q[W]);
-                if (sw > 0 ? iw > wlast : iw < lo_w) break;           // left the slab
-                const int32_t ix = fix_int(ls.Q[0]), iy = fix_int(ls.Q[1]), iz = fix_int(ls.Q[2]);
-                float fx = 0.f, fy = 0.f, fz = 0.f;
-                if (FILTER == VR_TRILINEAR) { fx = fix_frac(ls.Q[0]); fy = fix_frac(ls.Q[1]); fz = fix_frac(ls.Q[2]); }
-                float s;
-                if (use_lds) {
-                    // the clamp keeps every read inside the box
-                    const uint32_t lx = (uint32_t)min(max(ix - org[0], 0), lim[0]);
-                    const uint32_t ly = (uint32_t)min(max(iy - org[1], 0), lim[1]);
-                    const uint32_t lz = (uint32_t)min(max(iz - org[2], 0), lim[2]);
-                    s = lsample<FILTER>(box, lx * lstr[0] + ly * lstr[1] + lz * lstr[2], lstr[0], lstr[1], lstr[2],
-                                        fx, fy, fz);
-                } else {
-                    s = gsample<S, FILTER>(V, ix, iy, iz, fx, fy, fz);
-                }
-                ls.Q[0] += ls.D[0]; ls.Q[1] += ls.D[1]; ls.Q[2] += ls.D[2];
-                const bool go = consume<MODE>(ls, A, lut, pix, npix, s);
-                ++ls.k;
-                if (!go) { ls.stopped = true; active = false; break; }
-                if (ls.k >= ls.n) { active = false; break; }
+        // plan the next slab and issue its loads
+        cur = SW > 0 ? cur + sl.L : cur - sl.L;
+        if (remaining(cur) > 0) {
+            nxt = plan_slab<S, W, ORI, FILTER, SW>(SA, F, cur, sl.L, remaining(cur), nthr);
+            if (nxt.lds) {
+                wk.init(nxt, V, box, tid, nthr);
+                wk.load(raw, wk.row0);
             }
         }
-        c += sw;
+        if (active) {
+            const int64_t wedge = (int64_t)(SW > 0 ? sl.lo + sl.L : sl.lo) * 4294967296LL;   // in 32.32
+            const int64_t lim = SW > 0 ? min(wedge, qlast + 1) : max(wedge, qlast);
+            if (sl.lds) {
+                // element strides of the box (fastest axis 1) and the offset of
+                // corner index (0,0,0)
+                const int32_t esm = sl.Df, ess = sl.Df * sl.Dm;
+                const int32_t base = -((sl.fp0 - 1) + sl.b0[AM] * esm + sl.b0[AS] * ess);
+                const int32_t foot = FILTER == VR_TRILINEAR ? esm + ess + 1 : 0;
+                const uint32_t maxoff = (uint32_t)(sl.Df * sl.Dm * sl.Ds - 1 - foot);
+                lds_samples<MODE, FILTER, W, ORI, SW>(ls, A, lut, pix, npix, (const char *)box, esm, ess, base,
+                                                      maxoff, (uint32_t)(4 * esm), (uint32_t)(4 * ess), lim);
+            } else {
+                gather_samples<S, MODE, FILTER, W, SW>(ls, A, lut, pix, npix, lim);
+            }
+            if (ls.stopped || ls.k >= ls.n) active = false;
+        }
     }
 }
 
@@ -326,32 +489,6 @@ __device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0
         wlo = a;
         whi = b;
     }
-    // slab thickness: the largest L whose boxes at both ends of the
-    // traversal fit the budget (a perspective bundle widens with depth)
-    int32_t L = 0;
-    if (wlo <= whi && bundle_ok) {
-        for (int32_t cand = SA.lmax; cand >= 1; cand = (cand > 8 ? cand - 4 : cand - 1)) {
-            int64_t e[2];
-#pragma unroll
-            for (int end = 0; end < 2; ++end) {
-                const int32_t lo = (end == 0) == (sw > 0) ? whi - cand + 1 : wlo;
-                int32_t lu, hu, lv, hv, lw, hw;
-                slab_box(F, lo, cand, lu, hu, lv, hv, lw, hw);
-                int32_t q0[3], q1[3];
-                q0[0] = w == 0 ? lw : lu; q1[0] = w == 0 ? hw : hu;
-                q0[1] = w == 0 ? lu : (w == 1 ? lw : lv); q1[1] = w == 0 ? hu : (w == 1 ? hw : hv);
-                q0[2] = w == 2 ? lw : lv; q1[2] = w == 2 ? hw : hv;
-                constexpr int AF = ORI, AM = (ORI + 1) % 3, AS = (ORI + 2) % 3;
-                constexpr int EPC = 16 / (int)sizeof(S);
-                int32_t fp0, Df, Dm, Ds;
-                // the chunk origin shifts from slab to slab: allow for the widest alignment
-                box_dims<EPC>(q0[AF], q1[AF] + EPC - 1, q0[AM], q1[AM], q0[AS], q1[AS], fp0, Df, Dm, Ds);
-                e[end] = (int64_t)Df * Dm * Ds;
-            }
-            if (max(e[0], e[1]) <= SA.cap) { L = cand; break; }
-        }
-    }
-
     if (MODE == VR_COMPOSITE) {   // table to LDS (after the FP64 set-up)
         for (int i = tid; i < A.lut.n; i += blockDim.x) lut[i] = A.lut.rgba[i];
         __syncthreads();
@@ -359,12 +496,17 @@ __device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0
     const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
     const int64_t pix = (int64_t)py * A.cam.tile_w + px;
 
-    if (L > 0) {
+    if (wlo <= whi && bundle_ok) {
         const bool active = reg;
-        const int32_t c0 = sw > 0 ? fdiv(wlo, L) : fdiv(whi, L);
-        if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI>(SA, F, ls, active, L, sw, c0, box, lut, pix, npix);
-        else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI>(SA, F, ls, active, L, sw, c0, box, lut, pix, npix);
-        else run_slabs<S, MODE, FILTER, 2, ORI>(SA, F, ls, active, L, sw, c0, box, lut, pix, npix);
+        if (sw > 0) {
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+            else run_slabs<S, MODE, FILTER, 2, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+        } else {
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+            else run_slabs<S, MODE, FILTER, 2, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+        }
     }
     // lanes outside the slab scheme (and any samples left over) march on
     // with direct gathers
@@ -390,11 +532,12 @@ __device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0
 }
 
 template <typename S, int MODE, int FILTER, int ORI>
-__global__ __launch_bounds__(256) void k_slab(SlabArgs SA) {
+__global__ __launch_bounds__(512) void k_slab(SlabArgs SA) {
     extern __shared__ float smem[];
     __shared__ int32_t red[16];
-    const uint32_t group = tile_order(blockIdx.x, gridDim.x, SA.m.order);
-    const int gbx = group % SA.m.groups_x, gby = group / SA.m.groups_x;
+    int32_t gbx, gby;
+    tile_xy(blockIdx.x, gridDim.x, SA.m.groups_x, (int32_t)(gridDim.x / (uint32_t)SA.m.groups_x), SA.m.order, gbx,
+            gby);
     slab_bundle<S, MODE, FILTER, ORI>(SA, gbx * SA.bw, gby * SA.bh, smem, red);
 }
 
@@ -402,7 +545,7 @@ __global__ __launch_bounds__(256) void k_slab(SlabArgs SA) {
 // bundle of every view is done (each workgroup exits once the counter passes
 // the item count).  Items are numbered view by view, largest views first.
 template <typename S, int MODE, int FILTER>
-__global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
+__global__ __launch_bounds__(512) void k_batch(BatchArgs B) {
     extern __shared__ float smem[];
     __shared__ int32_t red[16];
     __shared__ int32_t item_s;
@@ -458,7 +601,7 @@ hipError_t launch_reset_u32(uint32_t *p, int32_t n, hipStream_t s) {
 
 template <typename S, int MODE, int FILTER>
 static hipError_t launch_batch_t(const BatchArgs &a, int32_t groups, hipStream_t s) {
-    const size_t lds = (size_t)a.cap * 4 + (MODE == VR_COMPOSITE ? (size_t)a.lut_n * 16 : 0);
+    const size_t lds = (size_t)a.cap * 4 + 32 + (MODE == VR_COMPOSITE ? (size_t)a.lut_n * 16 : 0);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_batch<S, MODE, FILTER>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -525,12 +668,16 @@ hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t
     a.m = m;
     a.bw = bw;
     a.bh = bh;
-    a.cap = cap_floats;
+    // dynamic LDS = box + spare slot + table must fit next to the kernel's
+    // static LDS (under 1 KiB) in the 160 KiB of a CU
+    const int32_t avail = (160 * 1024 - 1024 - 32 - (mode == VR_COMPOSITE ? m.lut.n * 16 : 0)) / 4;
+    a.cap = cap_floats < avail ? cap_floats : avail;
     a.lmax = lmax;
     a.m.groups_x = (m.cam.tile_w + bw - 1) / bw;
     int gy = (m.cam.tile_h + bh - 1) / bh;
     dim3 g((unsigned)(a.m.groups_x * gy)), b((unsigned)(bw * bh));
-    size_t lds = (size_t)cap_floats * 4 + (mode == VR_COMPOSITE ? (size_t)m.lut.n * 16 : 0);
+    // box budget + one spare 8-float slot + the table (composite)
+    size_t lds = (size_t)a.cap * 4 + 32 + (mode == VR_COMPOSITE ? (size_t)m.lut.n * 16 : 0);
     switch (m.vol.dtype) {
         case VR_F32: return launch_slab_s<float>(a, mode, filter, g, b, lds, s);
         case VR_F16: return launch_slab_s<_Float16>(a, mode, filter, g, b, lds, s);

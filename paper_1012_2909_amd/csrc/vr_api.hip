@@ -204,14 +204,76 @@ MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const CamDev &ca
 // gather directly.
 static bool use_slab_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single) return false;
-    if (ctx->tune.path == 1 || ctx->tune.waves_per_group != 4) return false;
+    if (ctx->tune.path == 1 || ctx->tune.waves_per_group < 4) return false;
     if (ctx->tune.path == 2) return true;
     return p->mode == VR_MIP || p->ert_alpha >= 1.0f;
 }
 
+// Automatic LDS budget of the slab path (tuning lds_kib = 0).  Two
+// workgroups per CU (64 KiB each) keep more waves in flight; a view whose
+// bundles need very wide boxes (oblique to all three axes) would march its
+// far slabs with direct gathers at that budget, so it gets one workgroup per
+// CU with 144 KiB.  The estimate: the box at slab thickness 2 near the far
+// face of the cube, for bundles spread over the viewport.
+int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh) {
+    const double N[3] = {(double)v.nx, (double)v.ny, (double)v.nz};
+    const int32_t L = 2;
+    double worst = 0.0;
+    const int32_t sx = std::max(bw, c.tile_w / 12), sy = std::max(bh, c.tile_h / 9);
+    for (int32_t y0 = 0; y0 < c.tile_h; y0 += sy) {
+        for (int32_t x0 = 0; x0 < c.tile_w; x0 += sx) {
+            const int32_t x1 = std::min(x0 + bw, c.tile_w) - 1, y1 = std::min(y0 + bh, c.tile_h) - 1;
+            double o[4][3], d[4][3], dc[3] = {0, 0, 0};
+            for (int k = 0; k < 4; ++k) {
+                cam_ray(c, c.tile_x0 + ((k & 1) ? x1 : x0), c.tile_y0 + ((k & 2) ? y1 : y0), o[k][0], o[k][1],
+                        o[k][2], d[k][0], d[k][1], d[k][2]);
+                for (int a = 0; a < 3; ++a) dc[a] += d[k][a];
+            }
+            int w = 0;
+            for (int a = 1; a < 3; ++a)
+                if (std::fabs(dc[a]) > std::fabs(dc[w])) w = a;
+            // the bundle's central line against the cube
+            double tn = -1e300, tf = 1e300;
+            bool hit = true;
+            for (int a = 0; a < 3; ++a) {
+                const double oa = (o[0][a] + o[3][a]) * 0.5, da = dc[a] * 0.25;
+                if (da == 0.0) { hit = hit && oa >= 0.0 && oa <= N[a]; continue; }
+                const double ta = (0.0 - oa) / da, tb = (N[a] - oa) / da;
+                tn = std::max(tn, std::min(ta, tb));
+                tf = std::min(tf, std::max(ta, tb));
+            }
+            if (!hit || !(tf > tn) || std::fabs(dc[w]) < 0.8) continue;
+            const double t = tf - 0.02 * (tf - tn);
+            const double pw = (o[0][w] + o[3][w]) * 0.5 + t * dc[w] * 0.25;
+            const double lo = dc[w] > 0 ? pw - L : pw;
+            double ext[3];
+            ext[w] = L + 1;
+            for (int a = 0; a < 3; ++a) {
+                if (a == w) continue;
+                double mn = 1e300, mx = -1e300;
+                for (int k = 0; k < 4; ++k) {
+                    for (int e = 0; e < 2; ++e) {
+                        const double p = lo + 0.5 + e * L;
+                        const double q = o[k][a] + (p - o[k][w]) / d[k][w] * d[k][a];
+                        mn = std::min(mn, q);
+                        mx = std::max(mx, q);
+                    }
+                }
+                ext[a] = std::floor(mx) - std::floor(mn) + 2.0;
+            }
+            ext[v.ori] = std::ceil((ext[v.ori] + 4.0) / 4.0) * 4.0;   // 16-byte chunks, misaligned start
+            worst = std::max(worst, ext[0] * ext[1] * ext[2] * 4.0 / 1024.0);
+        }
+    }
+    return worst > 100.0 ? 144 : 64;
+}
+
 static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s) {
     if (use_slab_path(ctx, p)) {
-        int32_t cap = ctx->tune.lds_kib * 1024 / 4;
+        const int32_t kib = ctx->tune.lds_kib > 0
+                                ? ctx->tune.lds_kib
+                                : vr_auto_box_kib(a.cam, a.vol, a.packet_w, a.packet_h * a.waves);
+        int32_t cap = kib * 1024 / 4;
         return launch_slab(a, p->mode, p->filter, a.packet_w, a.packet_h * a.waves, cap, ctx->tune.slab_max, s);
     }
     return launch_march(a, p->mode, p->filter, s);
@@ -503,12 +565,12 @@ static bool tuning_valid(const vr_tuning &t) {
     bool unroll = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
     bool pg = t.persistent_groups >= 1 && t.persistent_groups <= 32;
     bool path = t.path >= 0 && t.path <= 2;
-    bool lds = t.lds_kib >= 8 && t.lds_kib <= 144;  // + 16 KiB table: within the 160 KiB of LDS
+    bool lds = t.lds_kib == 0 || (t.lds_kib >= 8 && t.lds_kib <= 144);  // 0: automatic per view
     bool slab = t.slab_max >= 1 && t.slab_max <= 64;
-    // the LDS-staged kernel is compiled for 256-thread workgroups
-    bool slab_shape = t.path != 2 || t.waves_per_group == 4;
+    // the LDS-staged kernels run 256- or 512-thread workgroups
+    bool slab_shape = t.path != 2 || t.waves_per_group >= 4;
     bool copy = t.copy >= -1 && t.copy <= 2;
-    bool order = t.order == 0 || t.order == 1;
+    bool order = t.order >= 0 && t.order <= 2;
     return shape && waves && unroll && pg && path && lds && slab && slab_shape && copy && order;
 }
 

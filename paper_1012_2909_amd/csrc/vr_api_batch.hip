@@ -89,7 +89,7 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *p, const vr_view *views
     int rc = vr_check_params(ctx, p);
     if (rc != VR_OK) return rc;
     if (!ctx->vol.single) return vr_fail(ctx, VR_EUNSUPPORTED, "batched rendering needs a one-brick layout");
-    if (ctx->tune.waves_per_group != 4) return vr_fail(ctx, VR_EUNSUPPORTED, "batched rendering uses 4-wave groups");
+    if (ctx->tune.waves_per_group < 4) return vr_fail(ctx, VR_EUNSUPPORTED, "batched rendering uses 4- or 8-wave groups");
     if (n_views < 0 || (n_views > 0 && !views)) return vr_fail(ctx, VR_EINVAL, "bad view list");
     if (p->mode == VR_COMPOSITE) {
         if (!luts || n_luts < 1) return vr_fail(ctx, VR_EINVAL, "tables are NULL");
@@ -119,7 +119,18 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *p, const vr_view *views
     a.queue = (uint32_t *)((char *)ws + table_bytes(n_views));
     a.bw = ctx->tune.packet_w;
     a.bh = ctx->tune.packet_h * ctx->tune.waves_per_group;
-    a.cap = ctx->tune.lds_kib * 1024 / 4;
+    // box budget, capped so that box + spare slot + table fit the 160 KiB of
+    // a CU beside the kernel's static LDS (under 1 KiB)
+    int32_t kib = ctx->tune.lds_kib;
+    if (kib <= 0) {                                   // automatic: the widest view decides
+        kib = 64;
+        for (const ViewDev &v : pl.table) {
+            VolDev vd = ctx->vol;
+            apply_copy(vd, v.ori);
+            kib = std::max(kib, vr_auto_box_kib(v.cam, vd, a.bw, a.bh));
+        }
+    }
+    a.cap = std::min<int32_t>(kib * 1024 / 4, (160 * 1024 - 1024 - 32 - a.lut_n * 16) / 4);
     a.lmax = ctx->tune.slab_max;
     const int32_t groups = std::max(1, std::min(ctx->cus * ctx->tune.persistent_groups, pl.total));
     hipStream_t s = (hipStream_t)stream;
@@ -274,7 +285,7 @@ static std::vector<vr_tuning> candidates(const vr_ctx *ctx, bool batch) {
                 for (int o : {0, 1}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, 4, 1, 48, 16, -1, o});
         }
         if (ctx->vol.single) {
-            for (int kib : {32, 64, 96, 144})
+            for (int kib : {0, 48, 64, 96, 144})
                 for (int L : {8, 16, 32})
                     for (int pg : batch ? std::vector<int>{1, 2, 4} : std::vector<int>{4})
                         c.push_back(vr_tuning{sh[0], sh[1], 4, 1, pg, 2, kib, L, -1, 1});

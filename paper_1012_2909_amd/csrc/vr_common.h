@@ -111,8 +111,8 @@ struct Ray {
 
 // Ray through full-frame pixel (col, row).  Scalars only: arrays written
 // through pointers on two branches would not stay in registers.
-__device__ __forceinline__ void cam_ray(const CamDev &c, int col, int row, double &ox, double &oy, double &oz,
-                                        double &dx, double &dy, double &dz) {
+__host__ __device__ __forceinline__ void cam_ray(const CamDev &c, int col, int row, double &ox, double &oy,
+                                                 double &oz, double &dx, double &dy, double &dz) {
     const double sx = (2.0 * (col + 0.5) / c.W - 1.0) * c.a;
     const double sy = (1.0 - 2.0 * (row + 0.5) / c.H) * c.b;
     const bool persp = c.kind == VR_PERSPECTIVE;
@@ -279,9 +279,33 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
 // Logical tile of hardware workgroup bid under a tile order (a bijection):
 //  0: each XCD takes one contiguous band of tiles (XCD-local L2 reuse);
 //  1: hardware order: neighbouring tiles run on different XCDs, so the work
-//     of a view whose volume covers only part of the frame spreads evenly.
-__device__ __forceinline__ uint32_t tile_order(uint32_t bid, uint32_t nblocks, int order) {
-    return order == 1 ? bid : xcd_remap(bid, nblocks);
+//     of a view whose volume covers only part of the frame spreads evenly;
+//  2: blocks of 4 x 4 tiles, each run on one XCD, the blocks dealt over the
+//     XCDs in turn: neighbouring tiles share their XCD's L2 (overlapping
+//     voxel boxes are fetched once) and the work still spreads evenly.
+// Workgroups are dealt to the XCDs round-robin by id (bid mod 8).
+__device__ __forceinline__ void tile_xy(uint32_t bid, uint32_t nblocks, int32_t gx, int32_t gy, int order,
+                                        int32_t &tx, int32_t &ty) {
+    if (order == 2) {
+        // enumeration E: strips of 4 tile rows, each walked column by column
+        // (16 consecutive E indices form a 4 x 4 block, or a compact block
+        // of a shorter last strip)
+        const uint32_t X = 8, B = 16, full = nblocks / (X * B) * (X * B);
+        uint32_t e = bid;
+        if (bid < full) {
+            const uint32_t x = bid % X, k = bid / X;
+            e = ((k / B) * X + x) * B + k % B;
+        }
+        const uint32_t strip = e / (4u * (uint32_t)gx);
+        const uint32_t h = min(4u, (uint32_t)gy - 4u * strip);
+        const uint32_t w = e - strip * 4u * (uint32_t)gx;
+        tx = (int32_t)(w / h);
+        ty = (int32_t)(4u * strip + w % h);
+        return;
+    }
+    const uint32_t g = order == 1 ? bid : xcd_remap(bid, nblocks);
+    tx = (int32_t)(g % (uint32_t)gx);
+    ty = (int32_t)(g / (uint32_t)gx);
 }
 
 }  // namespace vr

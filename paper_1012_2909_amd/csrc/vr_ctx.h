@@ -23,7 +23,7 @@ struct vr_ctx {
     vr_camera cam{};
     vr::CamDev camd{};
     // launch shape
-    vr_tuning tune{16, 4, 4, 2, 4, 0, 48, 16, -1, 1};
+    vr_tuning tune{16, 4, 4, 2, 4, 0, 0, 16, -1, 1};
     // pinned staging for small device tables, and the event of its last copy
     void *stage = nullptr;
     size_t stage_bytes = 0;
@@ -44,6 +44,7 @@ int vr_dev_check(vr_ctx *ctx, hipError_t e, const char *what);
 int vr_check_params(vr_ctx *ctx, const vr_render_params *p);
 int vr_need_state(vr_ctx *ctx, bool lut_needed);
 vr::MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const vr::CamDev &cam);
+int32_t vr_auto_box_kib(const vr::CamDev &c, const vr::VolDev &v, int32_t bw, int32_t bh);
 // Pinned host staging of at least `bytes`; waits for the previous copy out of
 // it first.  NULL on failure.
 void *vr_stage(vr_ctx *ctx, size_t bytes);

@@ -24,7 +24,7 @@ struct MarchArgs {
     int32_t waves;                // packets per workgroup (stacked vertically)
     int32_t groups_x;             // workgroups per tile row
     int32_t unroll;               // samples per inner iteration (direct path, one-brick layouts)
-    int32_t order;                // tile order (see tile_order)
+    int32_t order;                // tile order (see tile_xy)
 };
 
 // K0: transcode planes [z0, z1) of a float32 (z1-z0, ny, nx) source block

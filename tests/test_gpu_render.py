@@ -135,7 +135,10 @@ TUNES = [dict(path=1), dict(path=1, packet_w=8, packet_h=8, waves_per_group=8),
          dict(path=1, copy=0), dict(path=1, copy=1), dict(path=1, copy=2, unroll=2),
          dict(path=2, copy=0), dict(path=2, copy=1), dict(path=2, copy=2, lds_kib=96),
          dict(path=2, copy=1, lds_kib=8, slab_max=2), dict(path=1, order=0), dict(path=2, order=0),
-         dict(path=1, order=1, unroll=4)]
+         dict(path=1, order=1, unroll=4), dict(path=1, order=2), dict(path=2, order=2),
+         dict(path=2, order=2, packet_w=32, packet_h=2, lds_kib=64), dict(path=1, order=2, packet_w=4, packet_h=16),
+         dict(path=2, packet_w=32, packet_h=2, waves_per_group=8, lds_kib=128),
+         dict(path=2, packet_w=16, packet_h=4, waves_per_group=8, lds_kib=16, order=2)]
 
 
 @pytest.mark.parametrize("mode,filt", [("composite", "trilinear"), ("mip", "nearest"), ("mip", "trilinear")])
@@ -164,7 +167,9 @@ def test_paths_and_shapes_agree_bitwise(R, mode, filt):
                               rel=0 if mode == "composite" else TOL_MIP_REL, what="paths ref")
             for t in TUNES:
                 R.set_tuning(**{**base_t, **t})
-                img = R.render(mode=mode, filt=filt).cpu().numpy()
+                # NaN-filled output: a pixel that no workgroup writes shows up
+                out = torch.full(ref.shape, float("nan"), dtype=torch.float32, device="cuda")
+                img = R.render(mode=mode, filt=filt, out=out).cpu().numpy()
                 assert np.array_equal(img, ref), f"tuning {t} differs"
     finally:
         R.set_tuning(**base_t)
