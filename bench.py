@@ -62,6 +62,11 @@ def main():
     ap.add_argument("--tune-cache", default="/tmp/vrcube_tune.json", help="autotuner cache file ('' for none)")
     ap.add_argument("--measure-cache", default="/tmp/vrcube_bench_measure.json",
                     help="cache of the per-angle sample counts and touched blocks ('' for none)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP16/BF16-storage, batched and backward variants reported beside the main figure")
+    ap.add_argument("--workload", default="spectral8", choices=["spectral8", "bricked64"],
+                    help="spectral8: the headline 8 GiB cube at 1920x1080 (default); bricked64: the 64 GiB cube as "
+                         "256^3 bricks, 9600x5400 as 5x5 tiles")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -83,6 +88,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copy probe: 4 copies of 2 GiB (2 GiB read + 2 GiB written each)")
+        return
+    if args.workload == "bricked64":
+        run_bricked64(args)
         return
     spec = synth.CUBE_8GIB
     W, H = 1920, 1080
@@ -215,6 +223,9 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(vol, lut, cams[0], step, args.cpu_seconds)
+    variants = None
+    if not args.no_variants and args.storage == "f32":
+        variants = run_variants(R, vol, cams, lut, modes, samples, mean_ms, step)
 
     rec = {
         "metric": "G ray-samples/s + fps at 1920x1080 on 8 GiB cube; % HBM roofline",
@@ -241,9 +252,183 @@ def main():
         "load_volume": {"ms": round(load_ms, 3), "GBps_moved": round(load_gbs, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(rec), flush=True)
     R.close()
+
+
+def _time_ms(fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def run_variants(R, vol, cams, lut, modes, samples, fp32_ms, step):
+    """The storage, batching and differentiation forms of the renderer, each
+    beside the plain FP32 render on this GPU, with its accuracy against the
+    FP64 oracle on seeded pixels."""
+    import torch
+    import oracle
+    from paper_1012_2909_amd import synth, vr
+    from paper_1012_2909_amd.autograd import VolumeRenderFn   # noqa: F401  (the differentiable entry point)
+    out = {}
+    dev = torch.device("cuda", 0)
+    W, H = 1920, 1080
+    pix = synth.sample_pixels(W, H, 3000, 7)
+    # (1) FP16 / BF16 storage of the 8 GiB cube: 16 angles, both modes
+    for st in ("f16", "bf16"):
+        src = torch.from_numpy(vol).to(dev)
+        R.load_volume(src, storage=st, brick=0, orientations=3)
+        del src
+        torch.cuda.empty_cache()
+        R.set_lut(lut)
+        ms = {}
+        for name, kw in modes.items():
+            t = []
+            for c in cams:
+                R.set_camera(c)
+                o = torch.empty((H, W, 4) if name == "composite" else (H, W), device=dev)
+                t.append(_time_ms(lambda: R.render(out=o, **kw), 2))
+            ms[name] = float(np.mean(t))
+        R.set_camera(cams[0])
+        img = R.render(**modes["composite"]).cpu().numpy()
+        ref = oracle.render(vol, lut, cams[0], pixels=pix, step=step)
+        g = img[pix[:, 1], pix[:, 0]].astype(np.float64)
+        clean = ref["flags"] == 0
+        err = float(np.abs(g[clean] - ref["out"][clean]).max())
+        out[f"{st}_storage"] = {
+            "workload": "8 GiB cube, 1920x1080, 16 orbit angles", "storage_bytes": int(R.storage.numel()),
+            "ms_per_frame": {k: round(v, 3) for k, v in ms.items()},
+            "speedup_vs_f32": {k: round(fp32_ms[k] / ms[k], 3) for k in ms},
+            "gsamples_per_s": {k: round(float(np.mean(samples[k])) / (ms[k] * 1e-3) / 1e9, 2) for k in ms},
+            "composite_max_abs_err_vs_fp64_oracle_on_f32_cube": err, "bar": 2e-3,
+            "accuracy_sample": f"{int(clean.sum())} seeded pixels of the first angle"}
+        log(f"variant {st} storage: {out[f'{st}_storage']}")
+    R.storage = None
+    torch.cuda.empty_cache()
+    # (2) batched: 64 uneven views of the 512 MiB cube, FP16 storage, one
+    # persistent launch replayed from a HIP graph, against the same views one
+    # by one and against FP32 storage
+    spec = synth.CUBE_512MIB
+    v4 = synth.make_cube(spec)
+    bcams, bluts = synth.batch_views(spec.shape, 4, n_views=64)
+    res = {}
+    for st in ("f16", "f32"):
+        R.load_volume(torch.from_numpy(v4).to(dev), storage=st)
+        packed = R.stack_luts(bluts)
+        nsamp = 0
+        for c, l in zip(bcams, bluts):
+            R.set_lut(l)
+            R.set_camera(c)
+            nsamp += int(R.count_samples().to(torch.int64).sum().item())
+        s = torch.cuda.Stream()
+        outs = [torch.empty((c.tile[3], c.tile[2], 4), device=dev) for c in bcams]
+
+        def batch():
+            with torch.cuda.stream(s):
+                R.render_batch(bcams, packed, outs=outs, use_graph=True, stream=s)
+            s.synchronize()
+        t_graph = _time_ms(batch, 5)
+
+        def one_by_one():
+            for c, l in zip(bcams, bluts):
+                R.set_lut(l)
+                R.set_camera(c)
+                R.render()
+        t_single = _time_ms(one_by_one, 2)
+        res[st] = (t_graph, t_single, nsamp)
+        if st == "f16":
+            worst = 0.0
+            for i in range(0, 64, 8):
+                p = synth.sample_pixels(bcams[i].tile[2], bcams[i].tile[3], 200, 40 + i)
+                r_ = oracle.render(v4, bluts[i], bcams[i], pixels=p, step=step)
+                g = outs[i].cpu().numpy()[p[:, 1], p[:, 0]].astype(np.float64)
+                cl = r_["flags"] == 0
+                worst = max(worst, float(np.abs(g[cl] - r_["out"][cl]).max()))
+    out["batch_64_views_f16"] = {
+        "workload": "512x512x1024 cube, 64 orbit views of 256..1920 x 256..1080 px, random tables",
+        "graph_ms": round(res["f16"][0], 3), "one_by_one_ms": round(res["f16"][1], 3),
+        "graph_speedup_vs_one_by_one": round(res["f16"][1] / res["f16"][0], 2),
+        "f32_storage_graph_ms": round(res["f32"][0], 3),
+        "gsamples_per_s": round(res["f16"][2] / (res["f16"][0] * 1e-3) / 1e9, 2),
+        "composite_max_abs_err_vs_fp64_oracle_on_f32_cube": worst, "bar": 2e-3,
+        "accuracy_sample": "200 seeded pixels of every 8th view"}
+    log(f"variant batch: {out['batch_64_views_f16']}")
+    del v4
+    # (3) differentiation: forward with checkpoints + adjoint on the
+    # 128x128x256 cube at 1024x1024, against the plain forward
+    spec = synth.CUBE_DIFF
+    v5 = synth.make_cube(spec)
+    cam = synth.orbit_camera(spec.shape, seed=5, w=1024, h=1024)
+    R.load_volume(torch.from_numpy(v5).to(dev), orientations=1)
+    R.set_lut(lut)
+    R.set_camera(cam)
+    t_plain = _time_ms(lambda: R.render(), 5)
+    img, ws = R.render(save=True)
+    gimg = torch.ones_like(img)
+    gl = torch.zeros((lut.table.shape[0], 4), device=dev)
+    gv = torch.zeros(spec.shape, device=dev)
+    t_fwd = _time_ms(lambda: R.render(save=True, workspace=ws), 5)
+
+    def bwd():
+        gl.zero_()
+        gv.zero_()
+        R.render_backward(gimg, ws, gl, gv)
+    t_bwd = _time_ms(bwd, 5)
+    out["backward_128x128x256_1024x1024"] = {
+        "forward_ms": round(t_plain, 3), "forward_with_checkpoints_ms": round(t_fwd, 3),
+        "backward_ms": round(t_bwd, 3), "backward_over_forward": round(t_bwd / t_plain, 2),
+        "accuracy": "gradients vs the FP64 oracle adjoint within 1e-4 of the largest entry (GPU test suite)"}
+    log(f"variant backward: {out['backward_128x128x256_1024x1024']}")
+    return out
+
+
+def run_bricked64(args):
+    """The 64 GiB cube as 256^3 bricks (one-voxel apron), 9600x5400 as 5x5
+    tiles of 1920x1080: per tile, per-brick partial images then the
+    sort-last "over"; composite (ramp table with alpha / 64, early stop at
+    0.99) and trilinear MIP."""
+    import torch
+    from paper_1012_2909_amd import synth, vr
+    dev = torch.device("cuda", 0)
+    spec = synth.CUBE_64GIB
+    t = time.time()
+    vol = synth.make_cube(spec)
+    log(f"cube {spec.shape} generated in {time.time() - t:.1f}s")
+    R = vr.Renderer(0)
+    R.describe_volume(spec.shape, storage=args.storage, brick=256)
+    for z0 in range(0, spec.shape[0], 256):
+        R.load_slab(torch.from_numpy(vol[z0:z0 + 256]).to(dev), z0)
+    torch.cuda.synchronize()
+    lut = synth.lut_ramp(alpha_scale=1.0 / 64.0)
+    R.set_lut(lut)
+    frame = synth.orbit_camera(spec.shape, seed=3, w=9600, h=5400)
+    tiles = synth.tiles_5x5(frame)
+    res = {}
+    for mode in ("composite", "mip"):
+        samples = 0
+        for c in tiles:
+            R.set_camera(c)
+            samples += int(R.count_samples(mode=mode).to(torch.int64).sum().item())
+
+        def frame_render():
+            for c in tiles:
+                R.set_camera(c)
+                R.render_bricked(mode=mode)
+        ms = _time_ms(frame_render, max(1, args.steps // 8))
+        res[mode] = {"ms_per_frame": round(ms, 2), "gsamples_per_s": round(samples / (ms * 1e-3) / 1e9, 2),
+                     "samples_per_frame": samples}
+        log(f"bricked {mode}: {res[mode]}")
+    print(json.dumps({"workload": "2048x2048x4096 float32 cube (64 GiB) as 256^3 bricks, 9600x5400 frame as 25 tiles",
+                      "storage": args.storage, "storage_bytes": int(R.storage.numel()), "modes": res}), flush=True)
 
 
 def cpu_baseline(vol, lut, cam, step, seconds):

@@ -134,26 +134,16 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs A) {
     if (A.taken) A.taken[pix] = k;
 }
 
-// Direct march over a one-brick layout, U samples per loop iteration: the
-// 8U gathers of a block are issued together, so a wave keeps U times more
-// loads in flight (this path is bound by load latency, not arithmetic).
+// Direct march of one lane's ray over a one-brick layout, U samples per
+// loop iteration: the 8U gathers of a block are issued together, so a wave
+// keeps U times more loads in flight (this path is bound by load latency,
+// not arithmetic).  The ray is set up; the table (composite) is in LDS.
 template <typename S, int MODE, int FILTER, int U>
-__global__ __launch_bounds__(256) void k_march_u(MarchArgs A) {
-    __shared__ float4 lut[1024];
-    int px, py;
-    const bool valid = lane_pixel(A, px, py);
-    const int64_t pix = (int64_t)py * A.cam.tile_w + px;
-    const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
-    Ray r{};
-    if (valid) make_ray(A.cam, A.vol, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
+__device__ __forceinline__ void march_u_run(const MarchArgs &A, const float4 *lut, const Ray &r, int64_t pix,
+                                            int64_t npix) {
     const int32_t n = r.n;
     int64_t Q[3], D[3];
     fix_start(r, A.step, 0, FILTER == VR_TRILINEAR ? 0.5 : 0.0, Q, D);
-    if (MODE == VR_COMPOSITE) {
-        for (int i = threadIdx.x; i < A.lut.n; i += blockDim.x) lut[i] = A.lut.rgba[i];
-        __syncthreads();
-    }
-    if (!valid) return;
     float m = -INFINITY;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     const bool use_log = (MODE == VR_COMPOSITE) && (A.trans == 1 || (A.trans == 2 && n > 1024));
@@ -200,6 +190,114 @@ __global__ __launch_bounds__(256) void k_march_u(MarchArgs A) {
     }
     if (A.counts) A.counts[pix] = k;
     if (A.taken) A.taken[pix] = k;
+}
+
+template <typename S, int MODE, int FILTER, int U>
+__global__ __launch_bounds__(256) void k_march_u(MarchArgs A) {
+    __shared__ float4 lut[1024];
+    int px, py;
+    const bool valid = lane_pixel(A, px, py);
+    const int64_t pix = (int64_t)py * A.cam.tile_w + px;
+    const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
+    Ray r{};
+    if (valid) make_ray(A.cam, A.vol, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
+    // the table goes to LDS after the FP64 set-up
+    if (MODE == VR_COMPOSITE) {
+        for (int i = threadIdx.x; i < A.lut.n; i += blockDim.x) lut[i] = A.lut.rgba[i];
+        __syncthreads();
+    }
+    if (!valid) return;
+    march_u_run<S, MODE, FILTER, U>(A, lut, r, pix, npix);
+}
+
+// K6, direct form: persistent workgroups pull (view, tile) items from the
+// same atomic queue as the LDS-staged batch kernel (views largest first) and
+// march each tile's rays with direct gathers; the table of the item's view is
+// reloaded into LDS when it changes.  Serves batches of early-stopping
+// composites, whose rays take few samples.  Each workgroup exits once the
+// counter passes the item count.
+template <typename S, int MODE, int FILTER, int U>
+__global__ __launch_bounds__(512) void k_batch_direct(BatchArgs B) {
+    __shared__ float4 lut[1024];
+    __shared__ int32_t item_s;
+    int32_t cur_lut = -1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ph = 64 / B.bw;                     // packet rows: bw x ph pixels per wave
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (int32_t)atomicAdd(B.queue, 1u);
+        __syncthreads();
+        const int32_t item = item_s;
+        if (item >= B.total_items) break;
+        int32_t lo = 0, hi = B.n_views - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (B.views[mid].tile_begin <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const ViewDev &V = B.views[lo];
+        if (MODE == VR_COMPOSITE && V.lut_index != cur_lut) {
+            const float4 *src = B.luts + (int64_t)V.lut_index * B.lut_n;
+            for (int i = threadIdx.x; i < B.lut_n; i += blockDim.x) lut[i] = src[i];
+            cur_lut = V.lut_index;
+        }
+        __syncthreads();   // table in place; item_s is rewritten only after the next barrier
+        MarchArgs A{};
+        A.cam = V.cam;
+        A.vol = B.vol;
+        A.vol.data = V.vdata;
+        A.vol.sx = V.vsx;
+        A.vol.sy = V.vsy;
+        A.vol.sz = V.vsz;
+        A.vol.ori = V.ori;
+        A.lut.n = B.lut_n;
+        A.lut.vmin = B.vmin;
+        A.lut.scale = B.scale;
+        A.step = B.step;
+        A.thr = B.thr;
+        A.ert = B.ert;
+        A.trans = B.trans;
+        A.out = V.out;
+        const int32_t t = item - V.tile_begin;
+        const int px = (t % V.tiles_x) * B.bw + lane % B.bw;
+        const int py = (t / V.tiles_x) * B.bh + wave * ph + lane / B.bw;
+        if (px < A.cam.tile_w && py < A.cam.tile_h) {
+            Ray r{};
+            make_ray(A.cam, A.vol, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
+            march_u_run<S, MODE, FILTER, U>(A, lut, r, (int64_t)py * A.cam.tile_w + px,
+                                            (int64_t)A.cam.tile_w * A.cam.tile_h);
+        }
+    }
+}
+
+template <typename S, int MODE, int FILTER>
+static hipError_t launch_batch_direct_u(const BatchArgs &a, int32_t unroll, int32_t groups, hipStream_t s) {
+    const dim3 g((unsigned)groups), b((unsigned)(a.bw * a.bh));
+    if (unroll == 4) hipLaunchKernelGGL((k_batch_direct<S, MODE, FILTER, 4>), g, b, 0, s, a);
+    else if (unroll == 2) hipLaunchKernelGGL((k_batch_direct<S, MODE, FILTER, 2>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_batch_direct<S, MODE, FILTER, 1>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_batch_direct_s(const BatchArgs &a, int32_t mode, int32_t filter, int32_t unroll,
+                                        int32_t groups, hipStream_t s) {
+    if (mode == VR_MIP) {
+        if (filter == VR_NEAREST) return launch_batch_direct_u<S, VR_MIP, VR_NEAREST>(a, unroll, groups, s);
+        return launch_batch_direct_u<S, VR_MIP, VR_TRILINEAR>(a, unroll, groups, s);
+    }
+    if (filter == VR_NEAREST) return launch_batch_direct_u<S, VR_COMPOSITE, VR_NEAREST>(a, unroll, groups, s);
+    return launch_batch_direct_u<S, VR_COMPOSITE, VR_TRILINEAR>(a, unroll, groups, s);
+}
+
+hipError_t launch_batch_direct(const BatchArgs &a, int32_t mode, int32_t filter, int32_t unroll, int32_t groups,
+                               hipStream_t s) {
+    if (groups <= 0 || a.total_items <= 0) return hipSuccess;
+    if (a.bw * a.bh > 512 || 64 % a.bw != 0 || a.bh % (64 / a.bw) != 0) return hipErrorInvalidValue;
+    switch (a.vol.dtype) {
+        case VR_F32: return launch_batch_direct_s<float>(a, mode, filter, unroll, groups, s);
+        case VR_F16: return launch_batch_direct_s<_Float16>(a, mode, filter, unroll, groups, s);
+        default: return launch_batch_direct_s<bf16_t>(a, mode, filter, unroll, groups, s);
+    }
 }
 
 // K7: mark the 8^3 blocks touched by each taken sample's interpolation

@@ -565,7 +565,11 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs B) {
         SlabArgs SA{};
         SA.m.cam = V.cam;
         SA.m.vol = B.vol;
-        apply_copy(SA.m.vol, V.ori);
+        SA.m.vol.data = V.vdata;
+        SA.m.vol.sx = V.vsx;
+        SA.m.vol.sy = V.vsy;
+        SA.m.vol.sz = V.vsz;
+        SA.m.vol.ori = V.ori;
         SA.m.lut.rgba = B.luts + (int64_t)V.lut_index * B.lut_n;
         SA.m.lut.n = B.lut_n;
         SA.m.lut.vmin = B.vmin;

@@ -60,6 +60,12 @@ int plan_views(vr_ctx *ctx, const vr_view *views, int32_t n, int32_t n_luts, Pla
         v.tiles_x = (views[i].cam.tile_w + bw - 1) / bw;
         v.tile_begin = (int32_t)total;
         v.ori = ctx->vol.orients == 3 ? (ctx->tune.copy >= 0 ? ctx->tune.copy : best_copy(v.cam.r)) : 0;
+        VolDev vd = ctx->vol;
+        apply_copy(vd, v.ori);
+        v.vdata = vd.data;
+        v.vsx = vd.sx;
+        v.vsy = vd.sy;
+        v.vsz = vd.sz;
         total += tiles[i];
     }
     if (total >= ((int64_t)1 << 31)) return vr_fail(ctx, VR_EINVAL, "too many pixels in one batch");
@@ -134,6 +140,15 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *p, const vr_view *views
     a.lmax = ctx->tune.slab_max;
     const int32_t groups = std::max(1, std::min(ctx->cus * ctx->tune.persistent_groups, pl.total));
     hipStream_t s = (hipStream_t)stream;
+    // the same path rule as single renders: early-stopping composites gather
+    // directly, long rays stage voxel boxes in LDS
+    const int32_t direct = ctx->tune.path == 1 ||
+                           (ctx->tune.path == 0 && p->mode == VR_COMPOSITE && p->ert_alpha < 1.0f);
+    const int32_t unroll = ctx->tune.unroll;
+    auto launch = [&](hipStream_t st) {
+        return direct ? launch_batch_direct(a, p->mode, p->filter, unroll, groups, st)
+                      : launch_batch(a, p->mode, p->filter, groups, st);
+    };
 
     // view table: pinned staging -> workspace, in stream order
     void *st = vr_stage(ctx, pl.table.size() * sizeof(ViewDev));
@@ -144,13 +159,13 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *p, const vr_view *views
 
     if (!use_graph) {
         e = launch_reset_u32(a.queue, 1, s);
-        if (e == hipSuccess) e = launch_batch(a, p->mode, p->filter, groups, s);
+        if (e == hipSuccess) e = launch(s);
         return vr_dev_check(ctx, e, "batch");
     }
     // graph: captured once per set of launch arguments, then replayed
     std::vector<int64_t> key = {(int64_t)(intptr_t)ws, (int64_t)(intptr_t)luts, (int64_t)(intptr_t)ctx->vol.data,
                                 n_views, pl.total, lut_n, n_luts, p->mode, p->filter, a.trans, a.ert, groups,
-                                a.bw, a.bh, a.cap, a.lmax};
+                                a.bw, a.bh, a.cap, a.lmax, direct, unroll};
     int64_t bits;
     std::memcpy(&bits, &p->step, 8);
     key.push_back(bits);
@@ -170,7 +185,7 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *p, const vr_view *views
         e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return vr_dev_check(ctx, e, "begin capture");
         hipError_t e1 = launch_reset_u32(a.queue, 1, ctx->capture_stream);
-        hipError_t e2 = e1 == hipSuccess ? launch_batch(a, p->mode, p->filter, groups, ctx->capture_stream) : e1;
+        hipError_t e2 = e1 == hipSuccess ? launch(ctx->capture_stream) : e1;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(ctx->capture_stream, &g);
         if (e2 != hipSuccess) { if (g) (void)hipGraphDestroy(g); return vr_dev_check(ctx, e2, "capture launch"); }
@@ -280,9 +295,12 @@ static std::vector<vr_tuning> candidates(const vr_ctx *ctx, bool batch) {
     std::vector<vr_tuning> c;
     const int shapes[3][2] = {{16, 4}, {64, 1}, {8, 8}};
     for (auto &sh : shapes) {
-        if (!batch) {
-            for (int u : {1, 2, 4})
-                for (int o : {0, 1}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, 4, 1, 48, 16, -1, o});
+        for (int u : {1, 2, 4}) {
+            if (batch) {
+                for (int pg : {1, 2, 4}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, pg, 1, 0, 16, -1, 1});
+            } else {
+                for (int o : {0, 1, 2}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, 4, 1, 0, 16, -1, o});
+            }
         }
         if (ctx->vol.single) {
             for (int kib : {0, 48, 64, 96, 144})

@@ -52,11 +52,16 @@ struct VolDev {
 
 // Padded extents of copy c of a one-brick layout: the fastest axis c rounded
 // up to a multiple of 8 elements, the other two n + 2.
+// Axis a of the cube's extent, by selects (no dynamic indexing of a local
+// array, which would put the whole structure in scratch memory).
+__host__ __device__ inline int64_t axis_n(const VolDev &v, int a) {
+    return a == 0 ? v.nx : (a == 1 ? v.ny : v.nz);
+}
+
 __host__ __device__ inline void copy_pitches(const VolDev &v, int c, int64_t &pf, int64_t &pm, int64_t &ps) {
-    const int64_t n[3] = {v.nx, v.ny, v.nz};
-    pf = (n[c] + 2 + 7) / 8 * 8;
-    pm = n[(c + 1) % 3] + 2;
-    ps = n[(c + 2) % 3] + 2;
+    pf = (axis_n(v, c) + 2 + 7) / 8 * 8;
+    pm = axis_n(v, (c + 1) % 3) + 2;
+    ps = axis_n(v, (c + 2) % 3) + 2;
 }
 
 // Point v (describing copy 0 of a layout) at copy o: base pointer, strides
@@ -65,14 +70,15 @@ __host__ __device__ inline void apply_copy(VolDev &v, int o) {
     if (v.orients < 3 || o <= 0 || o > 2) return;
     int64_t pf, pm, ps;
     copy_pitches(v, o, pf, pm, ps);
-    int64_t st[3];
-    st[o] = 1;
-    st[(o + 1) % 3] = pf;
-    st[(o + 2) % 3] = pf * pm;
-    v.data = (const char *)v.data + v.copy_off[o] * (v.dtype == VR_F32 ? 4 : 2);
-    v.sx = (int32_t)st[0];
-    v.sy = (int32_t)st[1];
-    v.sz = (int32_t)st[2];
+    // copy o stores axis o fastest, then o+1, then o+2 (cyclically)
+    const int64_t s_o = 1, s_o1 = pf, s_o2 = pf * pm;
+    const int64_t off = o == 1 ? v.copy_off[1] : v.copy_off[2];
+    v.data = (const char *)v.data + off * (v.dtype == VR_F32 ? 4 : 2);
+    // axis a has stride s_o if a == o, s_o1 if a == o+1, s_o2 if a == o+2 (mod 3)
+    auto st = [&](int a) { return a == o ? s_o : (a == (o + 1) % 3 ? s_o1 : s_o2); };
+    v.sx = (int32_t)st(0);
+    v.sy = (int32_t)st(1);
+    v.sz = (int32_t)st(2);
     v.ori = o;
 }
 

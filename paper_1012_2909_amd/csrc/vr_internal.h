@@ -78,6 +78,8 @@ struct ViewDev {
     int32_t tiles_x;      // bundles across the view
     int32_t tile_begin;   // first work item of the view
     int32_t ori;          // orientation copy the view reads
+    const void *vdata;    // that copy's element 0 and element strides (resolved on the host,
+    int32_t vsx, vsy, vsz;//   so the kernels select no structure field at run time)
 };
 struct BatchArgs {
     VolDev vol;           // copy 0 of a one-brick layout
@@ -96,6 +98,8 @@ struct BatchArgs {
     int32_t cap, lmax;    // LDS box budget (floats), thickest slab
 };
 hipError_t launch_batch(const BatchArgs &a, int32_t mode, int32_t filter, int32_t groups, hipStream_t s);
+hipError_t launch_batch_direct(const BatchArgs &a, int32_t mode, int32_t filter, int32_t unroll, int32_t groups,
+                               hipStream_t s);
 hipError_t launch_reset_u32(uint32_t *p, int32_t n, hipStream_t s);
 
 }  // namespace vr

@@ -7,13 +7,23 @@ import numpy as np
 #  - composite RGBA, FP32 storage: 1e-5 (the stated bar);
 #  - composite RGBA, FP16/BF16 storage against the oracle on the original
 #    FP32 cube: 2e-3; against the oracle on the storage-rounded cube: 1e-5;
-#  - trilinear MIP: the FP32 interpolation of 8 corners in 7 lerps rounds by
-#    at most ~4 ulp of the largest corner (4 * 2^-24 * |V|max, 2.4e-7 |V|max),
-#    the fixed-point position error is below 1e-9 voxel; we allow 1e-6 |s| + 1e-6;
+#  - trilinear MIP: the FP32 interpolation of 8 corners in 7 lerps, each a
+#    subtraction and an FMA, with weights converted from 32-bit fractions:
+#    one lerp level adds at most 5u M (u = 2^-24, M the largest corner
+#    magnitude: u|b-a| + u|r| + u f|b-a|), three levels 15u M, and the
+#    oracle's FP64 result is rounded once more (u |s|).  mip_tol(M) is that
+#    bound with M = the cube's largest magnitude; small test cubes use the
+#    looser-looking but there smaller 1e-6 |s| + 1e-6;
 #  - nearest MIP: bit-exact.
 TOL_COMPOSITE = 1e-5
 TOL_LOWP = 2e-3
 TOL_MIP_REL = 1e-6
+
+
+def mip_tol(vmax):
+    """Absolute bound of |GPU - oracle| for a trilinear MIP value of a cube
+    whose largest magnitude is vmax (see above)."""
+    return 16.0 * 2.0 ** -24 * float(vmax)
 
 
 def log(msg):

@@ -47,13 +47,21 @@ def _one_by_one(R, cams, luts, mode="composite"):
     return out
 
 
+@pytest.mark.parametrize("path", [0, 1, 2])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("mode", ["composite", "mip"])
-def test_batch_equals_single_views(R, cube, storage, mode):
-    log(f"case: batch storage={storage} mode={mode}")
+def test_batch_equals_single_views(R, cube, storage, mode, path):
+    """Every batch kernel (the automatic choice, direct gathers, LDS boxes)
+    reproduces the single-view renders bit for bit."""
+    log(f"case: batch storage={storage} mode={mode} path={path}")
     R.load_volume(torch.from_numpy(cube), storage=storage)
     cams, luts = _views(7, 9)
-    got = R.render_batch(cams, luts, mode=mode)
+    base = R.get_tuning()
+    R.set_tuning(path=path)
+    try:
+        got = R.render_batch(cams, luts, mode=mode)
+    finally:
+        R.set_tuning(**base)
     torch.cuda.synchronize()
     ref = _one_by_one(R, cams, luts, mode)
     for i, (g, r) in enumerate(zip(got, ref)):
@@ -127,7 +135,7 @@ def test_autotune_and_cache(R, cube, tmp_path):
     assert t2 == t1
     cams, luts = _views(5, 5)
     tb = R.autotune_batch(cams, luts, cache_path=path)
-    assert len(json.load(open(path))) == 2 and tb["path"] == 2
+    assert len(json.load(open(path))) == 2 and tb["path"] in (1, 2)
     # the tuned shapes still render correctly
     got = R.render_batch(cams, luts)
     torch.cuda.synchronize()
