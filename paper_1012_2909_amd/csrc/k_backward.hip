@@ -13,7 +13,8 @@
 // then chains through the table's linear interpolation (LDS-privatised table
 // gradient, flushed once per workgroup) and the trilinear weights (FP32
 // atomics into the (nz, ny, nx) gradient, corners clamped to the cube as the
-// clamp-to-edge sampling does).
+// clamp-to-edge sampling does; a lane sums the contributions of its
+// consecutive samples in one cell before adding them to memory).
 #include "vr_internal.h"
 
 namespace vr {
@@ -50,6 +51,28 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
         float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, P = 1.0f;
         const int nx = V.nx, ny = V.ny, nz = V.nz;
         const bool use_log = A.trans == 1 || (A.trans == 2 && r.n > 1024);
+        // voxel gradients of consecutive samples in the same cell are summed
+        // per lane and added to memory once the ray leaves the cell (the
+        // step is half a voxel: a cell holds two or three samples of a ray)
+        int32_t cx = INT32_MIN, cy = 0, cz = 0;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        auto flush = [&]() {
+            if (cx == INT32_MIN) return;
+            const int X0 = min(max(cx, 0), nx - 1), X1 = min(max(cx + 1, 0), nx - 1);
+            const int Y0 = min(max(cy, 0), ny - 1), Y1 = min(max(cy + 1, 0), ny - 1);
+            const int Z0 = min(max(cz, 0), nz - 1), Z1 = min(max(cz + 1, 0), nz - 1);
+            float *gv = B.grad_vol;
+            const int64_t r00 = ((int64_t)Z0 * ny + Y0) * nx, r10 = ((int64_t)Z0 * ny + Y1) * nx;
+            const int64_t r01 = ((int64_t)Z1 * ny + Y0) * nx, r11 = ((int64_t)Z1 * ny + Y1) * nx;
+            unsafeAtomicAdd(gv + r00 + X0, acc[0]);
+            unsafeAtomicAdd(gv + r00 + X1, acc[1]);
+            unsafeAtomicAdd(gv + r10 + X0, acc[2]);
+            unsafeAtomicAdd(gv + r10 + X1, acc[3]);
+            unsafeAtomicAdd(gv + r01 + X0, acc[4]);
+            unsafeAtomicAdd(gv + r01 + X1, acc[5]);
+            unsafeAtomicAdd(gv + r11 + X0, acc[6]);
+            unsafeAtomicAdd(gv + r11 + X1, acc[7]);
+        };
         for (int seg = (m - 1) / kSeg; seg >= 0; --seg) {
             const int k0 = seg * kSeg, k1 = min(k0 + kSeg, m);
             // forward replay of the segment from its checkpoint
@@ -101,21 +124,22 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
                     const float gs = (d0 * (Lb.x - La.x) + d1 * (Lb.y - La.y) + d2 * (Lb.z - La.z) +
                                       da * (Lb.w - La.w)) * A.lut.scale;
                     if (gs != 0.0f) {
-                        const int X0 = min(max(ix, 0), nx - 1), X1 = min(max(ix + 1, 0), nx - 1);
-                        const int Y0 = min(max(iy, 0), ny - 1), Y1 = min(max(iy + 1, 0), ny - 1);
-                        const int Z0 = min(max(iz, 0), nz - 1), Z1 = min(max(iz + 1, 0), nz - 1);
+                        if (ix != cx || iy != cy || iz != cz) {
+                            flush();
+                            cx = ix; cy = iy; cz = iz;
+                            for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+                        }
                         const float wx1 = fx, wx0 = 1.0f - fx, wy1 = fy, wy0 = 1.0f - fy, wz1 = fz, wz0 = 1.0f - fz;
-                        float *gv = B.grad_vol;
-                        const int64_t r00 = ((int64_t)Z0 * ny + Y0) * nx, r10 = ((int64_t)Z0 * ny + Y1) * nx;
-                        const int64_t r01 = ((int64_t)Z1 * ny + Y0) * nx, r11 = ((int64_t)Z1 * ny + Y1) * nx;
-                        unsafeAtomicAdd(gv + r00 + X0, gs * wz0 * wy0 * wx0);
-                        unsafeAtomicAdd(gv + r00 + X1, gs * wz0 * wy0 * wx1);
-                        unsafeAtomicAdd(gv + r10 + X0, gs * wz0 * wy1 * wx0);
-                        unsafeAtomicAdd(gv + r10 + X1, gs * wz0 * wy1 * wx1);
-                        unsafeAtomicAdd(gv + r01 + X0, gs * wz1 * wy0 * wx0);
-                        unsafeAtomicAdd(gv + r01 + X1, gs * wz1 * wy0 * wx1);
-                        unsafeAtomicAdd(gv + r11 + X0, gs * wz1 * wy1 * wx0);
-                        unsafeAtomicAdd(gv + r11 + X1, gs * wz1 * wy1 * wx1);
+                        const float g00 = gs * wz0 * wy0, g10 = gs * wz0 * wy1;
+                        const float g01 = gs * wz1 * wy0, g11 = gs * wz1 * wy1;
+                        acc[0] = fmaf(g00, wx0, acc[0]);
+                        acc[1] = fmaf(g00, wx1, acc[1]);
+                        acc[2] = fmaf(g10, wx0, acc[2]);
+                        acc[3] = fmaf(g10, wx1, acc[3]);
+                        acc[4] = fmaf(g01, wx0, acc[4]);
+                        acc[5] = fmaf(g01, wx1, acc[5]);
+                        acc[6] = fmaf(g11, wx0, acc[6]);
+                        acc[7] = fmaf(g11, wx1, acc[7]);
                     }
                 }
                 S0 = fmaf(a, c0 - S0, S0);
@@ -124,6 +148,7 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
                 P = P - a * P;
             }
         }
+        if (B.grad_vol) flush();
     }
     __syncthreads();
     if (B.grad_lut) {

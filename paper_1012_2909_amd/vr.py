@@ -13,7 +13,8 @@ import os
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvrcube.so")
+# the in-tree build; VRCUBE_LIB names another build of the same sources
+LIB_PATH = os.environ.get("VRCUBE_LIB") or os.path.join(HERE, "libvrcube.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
