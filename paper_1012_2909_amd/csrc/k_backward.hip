@@ -21,6 +21,11 @@ namespace vr {
 
 constexpr int kSeg = 64;        // samples per checkpoint segment
 constexpr int kBackThreads = 128;
+// Lanes of a workgroup take pixels kStride apart in x and y (16 x 8 lanes
+// over a 128 x 64 super-tile; the kStride^2 workgroups of a super-tile take
+// the offsets): neighbouring rays of a dense image share voxels, and lanes of
+// one atomic instruction then rarely hit the same address.
+constexpr int kStride = 8;
 
 __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
     extern __shared__ float smem[];
@@ -37,12 +42,16 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
     __syncthreads();
 
     const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
-    const int64_t pix = (int64_t)blockIdx.x * blockDim.x + tid;
+    const int32_t sgx = (A.cam.tile_w + 16 * kStride - 1) / (16 * kStride);
+    const int32_t st = (int32_t)blockIdx.x / (kStride * kStride), sub = (int32_t)blockIdx.x % (kStride * kStride);
+    const int px = (st % sgx) * 16 * kStride + sub % kStride + kStride * (tid % 16);
+    const int py = (st / sgx) * 8 * kStride + sub / kStride + kStride * (tid / 16);
+    const bool inside = px < A.cam.tile_w && py < A.cam.tile_h;
+    const int64_t pix = (int64_t)py * A.cam.tile_w + px;
     const VolDev &V = A.vol;
     int32_t m = 0;
-    if (pix < npix) m = A.taken[pix];
+    if (inside) m = A.taken[pix];
     if (m > 0) {
-        const int px = (int)(pix % A.cam.tile_w), py = (int)(pix / A.cam.tile_w);
         Ray r{};
         make_ray(A.cam, V, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
         int64_t Q0[3], D[3];
@@ -158,8 +167,9 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
 }
 
 hipError_t launch_backward(const BackArgs &a, hipStream_t s) {
-    const int64_t npix = (int64_t)a.m.cam.tile_w * a.m.cam.tile_h;
-    const unsigned blocks = (unsigned)((npix + kBackThreads - 1) / kBackThreads);
+    const int64_t sgx = (a.m.cam.tile_w + 16 * kStride - 1) / (16 * kStride);
+    const int64_t sgy = (a.m.cam.tile_h + 8 * kStride - 1) / (8 * kStride);
+    const unsigned blocks = (unsigned)(sgx * sgy * kStride * kStride);
     const size_t lds = (size_t)a.m.lut.n * 32 + (size_t)kSeg * kBackThreads * 4;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
