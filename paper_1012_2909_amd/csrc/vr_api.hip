@@ -261,7 +261,8 @@ int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh
                 }
                 ext[a] = std::floor(mx) - std::floor(mn) + 2.0;
             }
-            ext[v.ori] = std::ceil((ext[v.ori] + 4.0) / 4.0) * 4.0;   // 16-byte chunks, misaligned start
+            const double epc = v.dtype == VR_F32 ? 4.0 : 8.0;           // elements per 16-byte chunk
+            ext[v.ori] = std::ceil((ext[v.ori] + epc) / epc) * epc;       // whole chunks, misaligned start
             worst = std::max(worst, ext[0] * ext[1] * ext[2] * 4.0 / 1024.0);
         }
     }
