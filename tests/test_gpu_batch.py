@@ -142,3 +142,22 @@ def test_autotune_and_cache(R, cube, tmp_path):
     ref = _one_by_one(R, cams, luts)
     for g, r in zip(got, ref):
         assert np.array_equal(g.cpu().numpy(), r)
+
+
+def test_batch_with_one_pixel_and_empty_views(R, cube):
+    """1x1 viewports and a view that misses the cube, beside ordinary ones."""
+    R.load_volume(torch.from_numpy(cube))
+    lut = synth.lut_ramp()
+    big = synth.orbit_camera(SHAPE, seed=31, w=64, h=48)
+    one = big.with_tile(20, 30, 1, 1)
+    miss = synth.Camera(synth.ORTHO, (500.0, 500.0, -10.0), (500.0, 500.0, 0.0), (0.0, -1.0, 0.0),
+                        half_w=3.0, half_h=3.0, full_w=5, full_h=7)
+    cams = [one, big, miss, big.with_tile(63, 47, 1, 1)]
+    for mode in ("composite", "mip"):
+        got = R.render_batch(cams, [lut], mode=mode)
+        torch.cuda.synchronize()
+        ref = _one_by_one(R, cams, [lut] * 4, mode)
+        for i, (g, r) in enumerate(zip(got, ref)):
+            assert np.array_equal(g.cpu().numpy(), r), f"{mode} view {i}"
+        m = got[2].cpu().numpy()
+        assert (m == 0).all() if mode == "composite" else np.isneginf(m).all()

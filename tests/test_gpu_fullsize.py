@@ -76,6 +76,27 @@ def test_8gib_1920x1080_sampled(R, cube8, angle):
             assert_accept(got, res, TOL_COMPOSITE, what=what)
 
 
+def test_8gib_9600x5400_in_one_call_sampled(R, cube8):
+    """The largest viewport in one render call (the full 5x5-panel frame)."""
+    spec = synth.CUBE_8GIB
+    if R.shape != spec.shape or R.orientations != 3 or R.storage_dtype != "f32":
+        R.load_volume(torch.from_numpy(cube8), orientations=3)
+    lut = synth.lut_ramp()
+    R.set_lut(lut)
+    cam = synth.orbit_camera(spec.shape, seed=bench.angle_seeds()[3], w=9600, h=5400)
+    R.set_camera(cam)
+    for mode in ("composite", "mip"):
+        log(f"case: 8 GiB 9600x5400 {mode}")
+        img = R.render(mode=mode).cpu().numpy()
+        pix = _pixels(img, 800, 500)
+        res = oracle.render(cube8, lut, cam, mode=mode, pixels=pix, eps_stop=2e-5)
+        got = img[pix[:, 1], pix[:, 0]]
+        if mode == "mip":
+            assert_accept(got, res, mip_tol(np.abs(cube8).max()), what=f"9600x5400 {mode}")
+        else:
+            assert_accept(got, res, TOL_COMPOSITE, what=f"9600x5400 {mode}")
+
+
 @pytest.fixture(scope="module")
 def cube64():
     return synth.make_cube(synth.CUBE_64GIB)

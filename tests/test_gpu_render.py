@@ -216,6 +216,77 @@ def test_degenerate_sizes(R):
     assert np.isneginf(R.render(mode="mip").cpu().numpy()).all()
 
 
+@pytest.mark.parametrize("n_lut", [2, 1024])
+def test_table_size_extremes(R, n_lut):
+    """The smallest and the largest transfer-function tables.  The large one
+    is smooth (a few sine periods per channel): the 1e-5 bar is for tables
+    whose slope is that of the ramp's order; a random 1024-entry table has
+    slopes near 80 alpha per unit of sample value, which turns the FP32
+    sampling error (about 1e-7) into more than 1e-5."""
+    shape = (30, 26, 22)
+    vol = synth.make_cube(synth.CubeSpec(shape, 5, seed=21))
+    rng = np.random.default_rng(n_lut)
+    if n_lut == 2:
+        table = rng.uniform(0.0, 1.0, (n_lut, 4)).astype(np.float32)
+    else:
+        j = np.arange(n_lut)[:, None] / (n_lut - 1)
+        k = np.array([[2.0, 3.0, 1.5, 2.5]])
+        table = (0.5 + 0.5 * np.sin(2 * np.pi * k * j + rng.uniform(0, 6.28, (1, 4)))).astype(np.float32)
+    table[:, 3] *= 0.2
+    lut = synth.Lut(table, -3.0, 10.0)
+    cam = synth.orbit_camera(shape, seed=4, w=70, h=50)
+    for mode in ("composite", "mip"):
+        img = _render(R, vol, lut, cam, mode=mode)
+        res = oracle.render(vol, lut, cam, mode=mode, eps_stop=2e-5)
+        assert_accept(img, res, TOL_COMPOSITE if mode == "composite" else 1e-6,
+                      rel=0 if mode == "composite" else TOL_MIP_REL, what=f"table n={n_lut} {mode}")
+
+
+@pytest.mark.parametrize("step", [0.05, 3.0, 12.0])
+def test_step_extremes(R, step):
+    """A fine step (many samples per voxel), a coarse one, and one about as
+    long as the cube (no more than two samples per ray, most rays none)."""
+    shape = (20, 18, 16)
+    vol = synth.make_cube(synth.CubeSpec(shape, 4, seed=22))
+    lut = synth.lut_ramp(alpha_scale=0.1)
+    cam = synth.orbit_camera(shape, seed=9, w=48, h=40)
+    for mode, filt in [("composite", "trilinear"), ("mip", "trilinear"), ("mip", "nearest")]:
+        img = _render(R, vol, lut, cam, mode=mode, filt=filt, step=step)
+        res = oracle.render(vol, lut, cam, mode=mode, filt=filt, step=step, eps_stop=2e-5)
+        what = f"step {step} {mode}/{filt}"
+        if filt == "nearest":
+            assert_bitexact_mip(img, res, what)
+        else:
+            assert_accept(img, res, TOL_COMPOSITE if mode == "composite" else 1e-6,
+                          rel=0 if mode == "composite" else TOL_MIP_REL, what=what)
+
+
+def test_rays_in_the_faces_of_the_cube(R):
+    """Orthographic rays along z whose x or y lies exactly on a face of the
+    cube (x = 0, x = nx, y = 0, y = ny): a zero direction component keeps the
+    ray when its origin lies in the closed slab."""
+    shape = (12, 15, 15)                      # (nz, ny, nx)
+    vol = synth.make_cube(synth.CubeSpec(shape, 3, seed=23))
+    lut = synth.lut_ramp(alpha_scale=0.3)
+    # 16x16 pixels, half extent 8: pixel centres at x, y = 0, 1, ..., 15 exactly
+    # in FP64 (sx = c + 1/2 - 8), so the first and last columns and rows lie
+    # in the faces x = 0, x = 15, y = 0, y = 15
+    cam = synth.Camera(synth.ORTHO, (7.5, 7.5, -3.0), (7.5, 7.5, 0.0), (0.0, -1.0, 0.0),
+                       half_w=8.0, half_h=8.0, full_w=16, full_h=16)
+    for mode, filt in [("composite", "trilinear"), ("mip", "nearest"), ("mip", "trilinear")]:
+        img = _render(R, vol, lut, cam, mode=mode, filt=filt)
+        res = oracle.render(vol, lut, cam, mode=mode, filt=filt, eps_stop=2e-5)
+        what = f"face rays {mode}/{filt}"
+        if filt == "nearest":
+            assert_bitexact_mip(img, res, what)
+        else:
+            assert_accept(img, res, TOL_COMPOSITE if mode == "composite" else 1e-6,
+                          rel=0 if mode == "composite" else TOL_MIP_REL, what=what)
+        # the border columns and rows of pixels lie in the faces and take samples
+        hit = np.isfinite(img) if mode == "mip" else img[..., 3] > 0
+        assert hit[:, 0].any() and hit[:, -1].any() and hit[0, :].any() and hit[-1, :].any()
+
+
 # ---------------------------------------------------------------------------
 # FP16 / BF16 storage
 # ---------------------------------------------------------------------------
