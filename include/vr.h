@@ -126,8 +126,12 @@ typedef struct {
     int32_t packet_w, packet_h;   /* pixels per wavefront packet: 8x8, 16x4, 32x2, 64x1, 4x16 */
     int32_t waves_per_group;      /* 1, 2, 4, 8 (LDS-staged path: 4 or 8) */
     int32_t unroll;               /* direct path on one-brick layouts: samples per inner iteration, 1, 2, 4 */
-    int32_t persistent_groups;    /* batched launch: workgroups per CU, 1..32 */
-    int32_t path;                 /* 0 auto, 1 direct gathers, 2 LDS-staged voxel boxes (one-brick layouts) */
+    int32_t persistent_groups;    /* batched launch: workgroups per CU; path 3: packets per wave in a
+                                     workgroup's share; 1..32 */
+    int32_t path;                 /* 0 auto, 1 direct gathers, 2 LDS-staged voxel boxes (one-brick layouts),
+                                     3 direct gathers whose waves refill the lanes of finished rays with the
+                                     next pixels of their workgroup's share of packets, once a ballot shows
+                                     at most half of the lanes live (one-brick layouts, waves_per_group <= 4) */
     int32_t lds_kib;              /* LDS-staged path: voxel-box budget per workgroup, 8..144 KiB;
                                      0 = per view: 144 KiB for views oblique to all three axes, else 64 */
     int32_t slab_max;             /* LDS-staged path: thickest slab tried, 1..64 voxels */
@@ -201,7 +205,8 @@ int vr_set_camera(vr_ctx *ctx, const vr_camera *cam);
 /* ---- render ------------------------------------------------------------ */
 
 /* Workspace bytes vr_render needs for these params with the current camera
- * and volume (checkpoints when save_for_backward; work-queue counters). */
+ * and volume (samples taken and transmittance checkpoints when
+ * save_for_backward, else 0). */
 int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *params);
 
 /* Render the camera's viewport into out_dev: tile_h*tile_w*4 floats

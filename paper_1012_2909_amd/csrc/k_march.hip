@@ -210,6 +210,127 @@ __global__ __launch_bounds__(256) void k_march_u(MarchArgs A) {
     march_u_run<S, MODE, FILTER, U>(A, lut, r, pix, npix);
 }
 
+// K1/K2, compacting form (one-brick layouts).  A workgroup owns a share of
+// `share` consecutive packets (row-major over the tile) and its waves keep 64
+// rays in flight each.  A pass takes up to U samples of every live ray (the
+// gathers of a pass issued together); a lane whose ray has ended writes its
+// pixel and goes idle.  When a ballot shows at most refill_at live lanes, the
+// idle lanes take the next pixels of the share from a counter in LDS, each
+// ranked by a count of the idle lanes below it, so rays that stop early (the
+// opacity threshold, short chords near the cube's edges, misses) do not hold
+// lanes idle while the longest ray of a fixed packet finishes.  Pixel i of
+// the share is lane i%64 of its packet i/64.  Same per-ray arithmetic as
+// march_u_run, so the images are identical.  A wave leaves the loop once the
+// counter has passed the share's last pixel and its lanes are idle; every
+// pass of the loop takes a sample or advances the counter.
+template <typename S, int MODE, int FILTER, int U>
+__global__ __launch_bounds__(256) void k_march_c(CompactArgs C) {
+    __shared__ float4 lut[1024];
+    __shared__ uint32_t next;     // the share's pixel counter
+    const MarchArgs &A = C.m;
+    if (threadIdx.x == 0) next = 0u;
+    if (MODE == VR_COMPOSITE)
+        for (int i = threadIdx.x; i < A.lut.n; i += blockDim.x) lut[i] = A.lut.rgba[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
+    const int32_t p_first = (int32_t)blockIdx.x * C.share;
+    const int32_t n_share = min(C.share, C.packets - p_first) * 64;   // pixels of this share
+    const double h = FILTER == VR_TRILINEAR ? 0.5 : 0.0;
+    int64_t Q[3] = {0, 0, 0}, D[3] = {0, 0, 0};
+    int32_t n = 0, k = 0;
+    int64_t pix = 0;
+    float m = -INFINITY, T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    LogTrans lt;
+    bool use_log = false, live = false;
+    bool drained = false;         // the counter has passed the share's last pixel (uniform)
+    auto finish = [&]() {
+        if (A.out) {
+            if (MODE == VR_MIP) ((float *)A.out)[pix] = m;
+            else ((float4 *)A.out)[pix] = make_float4(C0, C1, C2, 1.0f - T);
+        }
+        if (A.counts) A.counts[pix] = k;
+        if (A.taken) A.taken[pix] = k;
+    };
+    for (;;) {
+        uint64_t lv = __ballot(live);
+        if (__popcll(lv) <= C.refill_at && !drained) {
+            const uint64_t idle = ~lv;
+            const int32_t nidle = __popcll(idle);
+            const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+            uint32_t got = 0;
+            if (lane == 0) got = atomicAdd(&next, (uint32_t)nidle);
+            got = (uint32_t)__shfl((int)got, 0, 64);
+            if ((int64_t)got + nidle >= n_share) drained = true;
+            const int32_t i = (int32_t)got + rank;
+            if (!live && i < n_share) {
+                const int32_t p = p_first + (i >> 6), j = i & 63;
+                const int px = (p % C.gxn) * A.packet_w + j % A.packet_w;
+                const int py = (p / C.gxn) * A.packet_h + j / A.packet_w;
+                if (px < A.cam.tile_w && py < A.cam.tile_h) {
+                    Ray r{};
+                    make_ray(A.cam, A.vol, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
+                    fix_start(r, A.step, 0, h, Q, D);
+                    n = r.n;
+                    k = 0;
+                    pix = (int64_t)py * A.cam.tile_w + px;
+                    m = -INFINITY;
+                    T = 1.0f;
+                    C0 = C1 = C2 = 0.0f;
+                    lt = LogTrans();
+                    use_log = (MODE == VR_COMPOSITE) && (A.trans == 1 || (A.trans == 2 && n > 1024));
+                    if (n > 0) live = true;
+                    else finish();
+                }
+            }
+            lv = __ballot(live);
+        }
+        if (lv == 0) {
+            if (drained) break;
+            continue;
+        }
+        if (!live) continue;
+        const int32_t cnt = min(U, n - k);
+        float v[U];
+        int64_t q0 = Q[0], q1 = Q[1], q2 = Q[2];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            if (FILTER == VR_TRILINEAR) { fx = fix_frac(q0); fy = fix_frac(q1); fz = fix_frac(q2); }
+            v[j] = j < cnt ? gsample<S, FILTER>(A.vol, fix_int(q0), fix_int(q1), fix_int(q2), fx, fy, fz) : 0.0f;
+            q0 += D[0]; q1 += D[1]; q2 += D[2];
+        }
+        bool stop = false;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (j >= cnt || stop) break;
+            const float s = v[j];
+            if (MODE == VR_MIP) {
+                m = fmaxf(m, s);
+            } else {
+                if (A.ckpt && ((k + j) & 63) == 0 && ((k + j) >> 6) < A.ckpt_segs)
+                    A.ckpt[(int64_t)((k + j) >> 6) * npix + pix] = T;
+                float4 c = lut_eval(lut, A.lut.n, A.lut.vmin, A.lut.scale, s);
+                float ta = T * c.w;
+                C0 = fmaf(ta, c.x, C0);
+                C1 = fmaf(ta, c.y, C1);
+                C2 = fmaf(ta, c.z, C2);
+                T = use_log ? lt.step(c.w) : T - ta;
+                if (A.ert && T <= A.thr) { stop = true; k += j + 1; }
+            }
+        }
+        if (!stop) {
+            k += cnt;
+            Q[0] = q0; Q[1] = q1; Q[2] = q2;
+        }
+        if (stop || k >= n) {
+            finish();
+            live = false;
+        }
+    }
+}
+
 // K6, direct form: persistent workgroups pull (view, tile) items from the
 // same atomic queue as the LDS-staged batch kernel (views largest first) and
 // march each tile's rays with direct gathers; the table of the item's view is
@@ -393,6 +514,48 @@ hipError_t launch_march(const MarchArgs &a, int32_t mode, int32_t filter, hipStr
         case VR_F32: launch_s<float>(a, mode, filter, g, b, s); break;
         case VR_F16: launch_s<_Float16>(a, mode, filter, g, b, s); break;
         default: launch_s<bf16_t>(a, mode, filter, g, b, s); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename S, int MODE, int FILTER>
+static void launch_compact_u(const CompactArgs &c, dim3 g, dim3 b, hipStream_t s) {
+    if (c.m.unroll == 4) hipLaunchKernelGGL((k_march_c<S, MODE, FILTER, 4>), g, b, 0, s, c);
+    else if (c.m.unroll == 2) hipLaunchKernelGGL((k_march_c<S, MODE, FILTER, 2>), g, b, 0, s, c);
+    else hipLaunchKernelGGL((k_march_c<S, MODE, FILTER, 1>), g, b, 0, s, c);
+}
+
+template <typename S>
+static void launch_compact_s(const CompactArgs &c, int32_t mode, int32_t filter, dim3 g, dim3 b, hipStream_t s) {
+    if (mode == VR_MIP) {
+        if (filter == VR_NEAREST) launch_compact_u<S, VR_MIP, VR_NEAREST>(c, g, b, s);
+        else launch_compact_u<S, VR_MIP, VR_TRILINEAR>(c, g, b, s);
+    } else {
+        if (filter == VR_NEAREST) launch_compact_u<S, VR_COMPOSITE, VR_NEAREST>(c, g, b, s);
+        else launch_compact_u<S, VR_COMPOSITE, VR_TRILINEAR>(c, g, b, s);
+    }
+}
+
+hipError_t launch_march_compact(const MarchArgs &a, int32_t mode, int32_t filter, int32_t packets_per_wave,
+                                hipStream_t s) {
+    if (!a.vol.single || a.waves < 1 || a.waves > 4 || packets_per_wave < 1 || packets_per_wave > 32 ||
+        a.packet_w * a.packet_h != 64)
+        return hipErrorInvalidValue;
+    CompactArgs c{};
+    c.m = a;
+    c.gxn = (a.cam.tile_w + a.packet_w - 1) / a.packet_w;
+    const int64_t gyn = (a.cam.tile_h + a.packet_h - 1) / a.packet_h;
+    const int64_t packets = (int64_t)c.gxn * gyn;
+    if (packets * 64 > 0x7fffffffLL) return hipErrorInvalidValue;
+    c.packets = (int32_t)packets;
+    c.share = a.waves * packets_per_wave;
+    c.refill_at = kCompactRefillAt;
+    if (packets == 0) return hipSuccess;
+    const dim3 g((unsigned)((packets + c.share - 1) / c.share)), b((unsigned)(64 * a.waves));
+    switch (a.vol.dtype) {
+        case VR_F32: launch_compact_s<float>(c, mode, filter, g, b, s); break;
+        case VR_F16: launch_compact_s<_Float16>(c, mode, filter, g, b, s); break;
+        default: launch_compact_s<bf16_t>(c, mode, filter, g, b, s); break;
     }
     return hipGetLastError();
 }

@@ -204,9 +204,14 @@ MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const CamDev &ca
 // gather directly.
 static bool use_slab_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single) return false;
-    if (ctx->tune.path == 1 || ctx->tune.waves_per_group < 4) return false;
+    if (ctx->tune.path == 1 || ctx->tune.path == 3 || ctx->tune.waves_per_group < 4) return false;
     if (ctx->tune.path == 2) return true;
     return p->mode == VR_MIP || p->ert_alpha >= 1.0f;
+}
+
+// The compacting direct kernel (path 3) on one-brick layouts.
+static bool use_compact_path(const vr_ctx *ctx) {
+    return ctx->vol.single && ctx->tune.path == 3 && ctx->tune.waves_per_group <= 4;
 }
 
 // Automatic LDS budget of the slab path (tuning lds_kib = 0).  Two
@@ -270,6 +275,7 @@ int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh
 }
 
 static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s) {
+    if (use_compact_path(ctx)) return launch_march_compact(a, p->mode, p->filter, ctx->tune.persistent_groups, s);
     if (use_slab_path(ctx, p)) {
         const int32_t kib = ctx->tune.lds_kib > 0
                                 ? ctx->tune.lds_kib
@@ -565,14 +571,17 @@ static bool tuning_valid(const vr_tuning &t) {
     bool waves = t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4 || t.waves_per_group == 8;
     bool unroll = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
     bool pg = t.persistent_groups >= 1 && t.persistent_groups <= 32;
-    bool path = t.path >= 0 && t.path <= 2;
+    bool path = t.path >= 0 && t.path <= 3;
     bool lds = t.lds_kib == 0 || (t.lds_kib >= 8 && t.lds_kib <= 144);  // 0: automatic per view
     bool slab = t.slab_max >= 1 && t.slab_max <= 64;
     // the LDS-staged kernels run 256- or 512-thread workgroups
     bool slab_shape = t.path != 2 || t.waves_per_group >= 4;
+    // the compacting kernel runs workgroups of at most 256 threads (and takes
+    // persistent_groups, 1..32, as packets per wave)
+    bool compact_shape = t.path != 3 || t.waves_per_group <= 4;
     bool copy = t.copy >= -1 && t.copy <= 2;
     bool order = t.order >= 0 && t.order <= 2;
-    return shape && waves && unroll && pg && path && lds && slab && slab_shape && copy && order;
+    return shape && waves && unroll && pg && path && lds && slab && slab_shape && compact_shape && copy && order;
 }
 
 int vr_set_tuning(vr_ctx *ctx, const vr_tuning *t) {

@@ -300,6 +300,8 @@ static std::vector<vr_tuning> candidates(const vr_ctx *ctx, bool batch) {
                 for (int pg : {1, 2, 4}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, pg, 1, 0, 16, -1, 1});
             } else {
                 for (int o : {0, 1, 2}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, 4, 1, 0, 16, -1, o});
+                if (ctx->vol.single && u > 1)
+                    for (int ppw : {1, 2}) c.push_back(vr_tuning{sh[0], sh[1], 4, u, ppw, 3, 0, 16, -1, 1});
             }
         }
         if (ctx->vol.single) {

@@ -34,6 +34,21 @@ hipError_t launch_transcode(const float *src, const VolDev &vol, int64_t z0, int
 // K1/K2: single-pass render of the camera's viewport.
 hipError_t launch_march(const MarchArgs &a, int32_t mode, int32_t filter, hipStream_t s);
 
+// K1/K2, compacting form (single-brick layouts): each workgroup owns
+// waves * packets_per_wave consecutive packets and its waves refill the lanes
+// of finished rays from an LDS counter.  packet_w * packet_h must be 64,
+// waves 1..4, packets_per_wave 1..32.
+struct CompactArgs {
+    MarchArgs m;
+    int32_t packets;      // packets over the tile
+    int32_t gxn;          // packets across the tile
+    int32_t share;        // packets per workgroup
+    int32_t refill_at;    // refill idle lanes once at most this many are live
+};
+constexpr int32_t kCompactRefillAt = 32;
+hipError_t launch_march_compact(const MarchArgs &a, int32_t mode, int32_t filter, int32_t packets_per_wave,
+                                hipStream_t s);
+
 // K1/K2 with LDS-staged voxel boxes (single-brick layouts).
 hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t bw, int32_t bh, int32_t cap_floats,
                        int32_t lmax, hipStream_t s);

@@ -138,7 +138,10 @@ TUNES = [dict(path=1), dict(path=1, packet_w=8, packet_h=8, waves_per_group=8),
          dict(path=1, order=1, unroll=4), dict(path=1, order=2), dict(path=2, order=2),
          dict(path=2, order=2, packet_w=32, packet_h=2, lds_kib=64), dict(path=1, order=2, packet_w=4, packet_h=16),
          dict(path=2, packet_w=32, packet_h=2, waves_per_group=8, lds_kib=128),
-         dict(path=2, packet_w=16, packet_h=4, waves_per_group=8, lds_kib=16, order=2)]
+         dict(path=2, packet_w=16, packet_h=4, waves_per_group=8, lds_kib=16, order=2),
+         dict(path=3), dict(path=3, unroll=2), dict(path=3, unroll=4, packet_w=64, packet_h=1, persistent_groups=1),
+         dict(path=3, packet_w=8, packet_h=8, waves_per_group=1, persistent_groups=32),
+         dict(path=3, packet_w=4, packet_h=16, waves_per_group=2, unroll=4, persistent_groups=2, copy=2)]
 
 
 @pytest.mark.parametrize("mode,filt", [("composite", "trilinear"), ("mip", "nearest"), ("mip", "trilinear")])
@@ -324,3 +327,76 @@ def test_low_precision_storage(R, storage):
     R.set_camera(cam)
     mipn = R.render(mode="mip", filt="nearest").cpu().numpy()
     assert_bitexact_mip(mipn, oracle.render(deq, lut, cam, mode="mip", filt="nearest"), f"{storage} nearest MIP")
+
+
+# ---------------------------------------------------------------------------
+# the compacting direct kernel (path 3): refilled lanes, same arithmetic
+# ---------------------------------------------------------------------------
+def _saved(ws, npix, segs):
+    """(samples taken, checkpoints) of a save_for_backward workspace; a
+    checkpoint slot counts only where the ray reached its sample."""
+    off = (npix * 4 + 255) // 256 * 256
+    taken = ws[:npix * 4].view(torch.int32).cpu().numpy().copy()
+    ck = ws[off:off + segs * npix * 4].view(torch.float32).cpu().numpy().reshape(segs, npix).copy()
+    written = np.arange(segs)[:, None] * 64 < taken[None, :]
+    return taken, np.where(written, ck, 0.0)
+
+
+@pytest.mark.parametrize("w,h", [(150, 110), (1, 1), (67, 3)])
+def test_compacting_path_matches_direct(R, w, h):
+    """Path 3 renders the images, sample counts and checkpoints of path 1 bit
+    for bit: composite with and without the early stop, log transmittance,
+    nearest and trilinear MIP; ragged viewports whose packets run past the
+    tile; shares of 1 to 32 packets per wave."""
+    shape = (70, 45, 52)
+    vol = synth.make_cube(synth.CubeSpec(shape, 10, seed=23, fwhm_z=(4.0, 20.0)))
+    lut = synth.lut_ramp(alpha_scale=0.25)
+    R.load_volume(torch.from_numpy(vol))
+    R.set_lut(lut)
+    base_t = R.get_tuning()
+    cases = [dict(mode="composite"), dict(mode="composite", ert=1.0), dict(mode="composite", trans="log"),
+             dict(mode="mip", filt="nearest"), dict(mode="mip")]
+    shares = (dict(unroll=2), dict(unroll=4, packet_w=8, packet_h=8, persistent_groups=1),
+              dict(unroll=1, waves_per_group=1, persistent_groups=32), dict(unroll=2, waves_per_group=2,
+                                                                         packet_w=64, packet_h=1, persistent_groups=3))
+    try:
+        for seed in (3, 9):
+            cam = synth.orbit_camera(shape, seed=seed, w=150, h=110)
+            R.set_camera(cam.with_tile(150 - w, 0, w, h) if (w, h) != (150, 110) else cam)
+            for kw in cases:
+                R.set_tuning(**{**base_t, "path": 1, "unroll": 2})
+                ref = R.render(**kw).cpu().numpy()
+                for t in shares:
+                    R.set_tuning(**{**base_t, "path": 3, **t})
+                    out = torch.full(ref.shape, float("nan"), dtype=torch.float32, device="cuda")
+                    img = R.render(out=out, **kw).cpu().numpy()
+                    assert np.array_equal(img, ref), f"seed {seed} {kw} {t}"
+            # save_for_backward: samples taken and transmittance checkpoints
+            R.set_tuning(**{**base_t, "path": 1, "unroll": 2})
+            nws = int(R.render(save=True)[1].numel())
+            npix = w * h
+            segs = (nws - (npix * 4 + 255) // 256 * 256) // (npix * 4)
+            got = []
+            for path in (1, 3):
+                R.set_tuning(**{**base_t, "path": path, "unroll": 2})
+                ws = torch.full((nws,), 255, dtype=torch.uint8, device="cuda")
+                img, ws = R.render(save=True, workspace=ws)
+                cnt = R.count_samples().cpu().numpy().reshape(-1)
+                got.append((img.cpu().numpy(), *_saved(ws, npix, segs), cnt))
+            for a, b in zip(got[0], got[1]):
+                assert np.array_equal(a, b)
+            assert np.array_equal(got[1][1], got[1][3])     # samples taken == samples counted
+    finally:
+        R.set_tuning(**base_t)
+
+
+def test_compacting_path_against_oracle(R, cube64):
+    lut = synth.lut_ramp()
+    cam = synth.orbit_camera(cube64.shape, seed=6, w=96, h=80)
+    base_t = R.get_tuning()
+    try:
+        R.set_tuning(**{**base_t, "path": 3})
+        img = _render(R, cube64, lut, cam)
+        assert_accept(img, oracle.render(cube64, lut, cam, eps_stop=2e-5), TOL_COMPOSITE, what="path 3")
+    finally:
+        R.set_tuning(**base_t)
