@@ -214,6 +214,19 @@ static bool use_compact_path(const vr_ctx *ctx) {
     return ctx->vol.single && ctx->tune.path == 3 && ctx->tune.waves_per_group <= 4;
 }
 
+// MIP in object order (path 4) on one-brick layouts; it keeps per-pixel ray
+// records in the workspace.  The automatic choice (path 0 with the automatic
+// LDS budget) takes it for views oblique to all three axes, whose slab boxes
+// would need the large budget: there the blocks read each voxel about once,
+// while the bundles' boxes overlap most.
+static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
+    if (!ctx->vol.single || p->mode != VR_MIP || !ctx->has_camera) return false;
+    if (ctx->tune.path == 4) return true;
+    if (ctx->tune.path != 0 || ctx->tune.lds_kib != 0 || ctx->tune.waves_per_group < 4) return false;
+    return vr_auto_box_kib(ctx->camd, ctx->vol, ctx->tune.packet_w,
+                           ctx->tune.packet_h * ctx->tune.waves_per_group) > 64;
+}
+
 // Automatic LDS budget of the slab path (tuning lds_kib = 0).  Two
 // workgroups per CU (64 KiB each) keep more waves in flight; a view whose
 // bundles need very wide boxes (oblique to all three axes) would march its
@@ -475,8 +488,9 @@ int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *p) 
     if (!ctx || !p) return fail(ctx, VR_EINVAL, "NULL argument");
     if (!ctx->vol_loaded || !ctx->has_camera) return fail(ctx, VR_ESTATE, "volume and camera first");
     if (check_params(const_cast<vr_ctx *>(ctx), p) != VR_OK) return VR_EINVAL;
-    if (!p->save_for_backward) return 0;
     int64_t npix = (int64_t)ctx->cam.tile_w * ctx->cam.tile_h;
+    if (use_block_path(ctx, p)) return mip_blocks_workspace(npix);
+    if (!p->save_for_backward) return 0;
     return align256(npix * 4) + ckpt_segs(ctx, p) * npix * 4;
 }
 
@@ -496,6 +510,20 @@ int vr_render(vr_ctx *ctx, const vr_render_params *p, float *out_dev, void *ws, 
         a.taken = (int32_t *)ws;
         a.ckpt = (float *)((char *)ws + align256(npix * 4));
         a.ckpt_segs = (int32_t)ckpt_segs(ctx, p);
+    }
+    if (use_block_path(ctx, p)) {
+        // without room for the ray records the marching kernels render the same image
+        const int64_t need = mip_blocks_workspace((int64_t)ctx->cam.tile_w * ctx->cam.tile_h);
+        if (ws && ws_bytes >= need) {
+            MarchArgs b = a;
+            b.vol = ctx->vol;                 // the x-fastest copy
+            // tuning for this path: lds_kib 8..63 takes 32x16x16 blocks (42 KiB of LDS), else 32x32x16
+            // (79 KiB); waves_per_group 8 runs 512 threads on the larger blocks; slab_max blocks per run
+            const vr_tuning &t = ctx->tune;
+            const int32_t shape = (t.lds_kib > 0 && t.lds_kib < 64) ? 0 : (t.waves_per_group >= 8 ? 2 : 1);
+            const int32_t run = t.path == 4 ? t.slab_max : 8;
+            return dev_check(ctx, launch_mip_blocks(b, p->filter, ws, run, shape, (hipStream_t)stream), "render");
+        }
     }
     return dev_check(ctx, dispatch_render(ctx, a, p, (hipStream_t)stream), "render");
 }
@@ -571,7 +599,7 @@ static bool tuning_valid(const vr_tuning &t) {
     bool waves = t.waves_per_group == 1 || t.waves_per_group == 2 || t.waves_per_group == 4 || t.waves_per_group == 8;
     bool unroll = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
     bool pg = t.persistent_groups >= 1 && t.persistent_groups <= 32;
-    bool path = t.path >= 0 && t.path <= 3;
+    bool path = t.path >= 0 && t.path <= 4;
     bool lds = t.lds_kib == 0 || (t.lds_kib >= 8 && t.lds_kib <= 144);  // 0: automatic per view
     bool slab = t.slab_max >= 1 && t.slab_max <= 64;
     // the LDS-staged kernels run 256- or 512-thread workgroups

@@ -49,6 +49,14 @@ constexpr int32_t kCompactRefillAt = 32;
 hipError_t launch_march_compact(const MarchArgs &a, int32_t mode, int32_t filter, int32_t packets_per_wave,
                                 hipStream_t s);
 
+// K8: MIP in object order (single-brick layouts, x-fastest copy in a.vol):
+// ray records of the tile in ws (mip_blocks_workspace bytes), blocks of the
+// volume staged in LDS, one atomic maximum per (pixel, block); run = blocks
+// along x per workgroup; shape 0..2 selects the block edges and threads.
+int64_t mip_blocks_workspace(int64_t npix);
+hipError_t launch_mip_blocks(const MarchArgs &a, int32_t filter, void *ws, int32_t run, int32_t shape,
+                             hipStream_t s);
+
 // K1/K2 with LDS-staged voxel boxes (single-brick layouts).
 hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t bw, int32_t bh, int32_t cap_floats,
                        int32_t lmax, hipStream_t s);

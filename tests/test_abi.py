@@ -140,11 +140,13 @@ def test_argument_errors(hctx):
     # the LDS-staged path runs 4- or 8-wave groups only
     assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 2, 1, 4, 2, 64, 16, -1, 1))) == vr.EINVAL
     assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 8, 1, 4, 2, 64, 16, -1, 1))) == vr.OK
-    # the compacting path (3) runs groups of at most 4 waves, shares of 1..32 packets per wave; no path 4
+    # the compacting path (3) runs groups of at most 4 waves, shares of 1..32 packets per wave;
+    # path 4 is MIP in object order; no path 5
     assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 4, 2, 8, 3, 0, 16, -1, 1))) == vr.OK
     assert L.vr_set_tuning(h, C.byref(vr.Tuning(8, 8, 1, 4, 32, 3, 0, 16, -1, 1))) == vr.OK
     assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 8, 2, 4, 3, 0, 16, -1, 1))) == vr.EINVAL
-    assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 4, 2, 4, 4, 0, 16, -1, 1))) == vr.EINVAL
+    assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 4, 2, 4, 4, 0, 16, -1, 1))) == vr.OK
+    assert L.vr_set_tuning(h, C.byref(vr.Tuning(16, 4, 4, 2, 4, 5, 0, 16, -1, 1))) == vr.EINVAL
 
 
 def test_params_errors(hctx):

@@ -141,7 +141,8 @@ TUNES = [dict(path=1), dict(path=1, packet_w=8, packet_h=8, waves_per_group=8),
          dict(path=2, packet_w=16, packet_h=4, waves_per_group=8, lds_kib=16, order=2),
          dict(path=3), dict(path=3, unroll=2), dict(path=3, unroll=4, packet_w=64, packet_h=1, persistent_groups=1),
          dict(path=3, packet_w=8, packet_h=8, waves_per_group=1, persistent_groups=32),
-         dict(path=3, packet_w=4, packet_h=16, waves_per_group=2, unroll=4, persistent_groups=2, copy=2)]
+         dict(path=3, packet_w=4, packet_h=16, waves_per_group=2, unroll=4, persistent_groups=2, copy=2),
+         dict(path=4)]
 
 
 @pytest.mark.parametrize("mode,filt", [("composite", "trilinear"), ("mip", "nearest"), ("mip", "trilinear")])
@@ -398,5 +399,53 @@ def test_compacting_path_against_oracle(R, cube64):
         R.set_tuning(**{**base_t, "path": 3})
         img = _render(R, cube64, lut, cam)
         assert_accept(img, oracle.render(cube64, lut, cam, eps_stop=2e-5), TOL_COMPOSITE, what="path 3")
+    finally:
+        R.set_tuning(**base_t)
+
+
+# ---------------------------------------------------------------------------
+# MIP in object order (path 4): blocks of the volume, one atomic maximum per
+# (pixel, block); equal to the marching kernels bit for bit
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,orient", [("f32", 3), ("f32", 1), ("f16", 3), ("bf16", 1)])
+def test_object_order_mip_matches_marching(R, storage, orient):
+    shape = (70, 45, 52)        # no axis a multiple of the block edges
+    vol = synth.make_cube(synth.CubeSpec(shape, 10, seed=29, fwhm_z=(4.0, 20.0)))
+    R.load_volume(torch.from_numpy(vol), storage=storage, orientations=orient)
+    R.set_lut(synth.lut_ramp())
+    cams = [synth.orbit_camera(shape, seed=s, w=150, h=110) for s in (1, 4, 8)]
+    cams += [
+        # orthographic, oblique
+        synth.Camera(synth.ORTHO, (-40.0, 30.0, 20.0), (26.0, 22.5, 35.0), (0.0, -1.0, 0.0),
+                     half_w=50.0, half_h=40.0, full_w=150, full_h=110),
+        # orthographic along z and along x (rays in block faces and with zero steps)
+        synth.Camera(synth.ORTHO, (26.0, 22.5, -10.0), (26.0, 22.5, 35.0), (0.0, -1.0, 0.0),
+                     half_w=30.0, half_h=25.0, full_w=64, full_h=48),
+        synth.Camera(synth.ORTHO, (-10.0, 22.5, 35.0), (26.0, 22.5, 35.0), (0.0, -1.0, 0.0),
+                     half_w=40.0, half_h=25.0, full_w=64, full_h=48),
+        # eye inside the cube: blocks behind the eye
+        synth.Camera(synth.PERSPECTIVE, (30.0, 20.0, 30.0), (10.0, 25.0, 60.0), (0.0, -1.0, 0.0),
+                     fovy_deg=80.0, full_w=96, full_h=64),
+        # close perspective camera: blocks near the eye plane
+        synth.Camera(synth.PERSPECTIVE, (26.0, 22.5, -3.0), (26.0, 22.5, 35.0), (0.0, -1.0, 0.0),
+                     fovy_deg=100.0, full_w=96, full_h=64),
+    ]
+    cams.append(cams[0].with_tile(37, 21, 61, 53))       # a viewport inside the frame
+    base_t = R.get_tuning()
+    try:
+        for i, cam in enumerate(cams):
+            R.set_camera(cam)
+            for filt in ("nearest", "trilinear"):
+                R.set_tuning(**{**base_t, "path": 1})
+                ref = R.render(mode="mip", filt=filt).cpu().numpy()
+                # block shapes 32x32x16 (256 and 512 threads) and 32x16x16; runs of 16, 1 and 3 blocks
+                for t in (dict(), dict(waves_per_group=8, slab_max=1), dict(lds_kib=32, slab_max=3)):
+                    R.set_tuning(**{**base_t, "path": 4, **t})
+                    out = torch.full(ref.shape, float("nan"), dtype=torch.float32, device="cuda")
+                    img = R.render(mode="mip", filt=filt, out=out).cpu().numpy()
+                    assert np.array_equal(img, ref), f"camera {i} {filt} {t}: {np.sum(img != ref)} pixels differ"
+            if storage == "f32" and orient == 3 and i in (0, 6):
+                o = oracle.render(vol, synth.lut_ramp(), cam, mode="mip", filt="nearest")
+                assert_bitexact_mip(R.render(mode="mip", filt="nearest").cpu().numpy(), o, f"object order {i}")
     finally:
         R.set_tuning(**base_t)
