@@ -43,7 +43,7 @@ def kernel_revision():
     """Hash of the kernels' sources: stored traffic counters are only valid
     for the revision they were measured on."""
     h = hashlib.sha1()
-    for f in ("k_slab.hip", "k_march.hip", "vr_common.h"):
+    for f in ("k_slab.hip", "k_march.hip", "k_mipblk.hip", "vr_common.h", "vr_api.hip"):
         h.update(open(os.path.join(ROOT, "paper_1012_2909_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 
@@ -214,7 +214,11 @@ def main():
                 traffic = e["bytes_per_launch"]
         except (OSError, ValueError, KeyError):
             traffic = None
-    kname = {"mip": "k_slab<MIP>" if tunes["mip"]["path"] != 1 else "k_march<MIP>",
+    mip_kernels = {0: "MIP frame: k_slab (ray bundles), or k_raytable + k_mip_blocks + k_mip_decode (object order) "
+                      "on views oblique to all three axes",
+                   1: "k_march<MIP>", 2: "k_slab<MIP>", 3: "k_march_c<MIP>",
+                   4: "k_raytable + k_mip_blocks + k_mip_decode"}
+    kname = {"mip": mip_kernels.get(tunes["mip"]["path"], "MIP"),
              "composite": "k_march<COMPOSITE>" if tunes["composite"]["path"] != 2 else "k_slab<COMPOSITE>"}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname[dom],
@@ -248,6 +252,8 @@ def main():
         "gsamples_per_s": {k: round(v, 2) for k, v in gsps.items()},
         "samples_per_frame_mean": {n: int(np.mean(samples[n])) for n in modes},
         "hbm_roofline_frac": {n: round(v, 4) for n, v in frac.items()},
+        "ms_per_angle": {n: [round(float(np.mean([per_launch[n][k] for k in range(args.steps) if k % N_ANGLES == a])), 3)
+                             for a in range(min(N_ANGLES, args.steps))] for n in modes},
         "launch_shapes": tunes,
         "load_volume": {"ms": round(load_ms, 3), "GBps_moved": round(load_gbs, 1)},
         "roofline": roof,

@@ -216,15 +216,21 @@ static bool use_compact_path(const vr_ctx *ctx) {
 
 // MIP in object order (path 4) on one-brick layouts; it keeps per-pixel ray
 // records in the workspace.  The automatic choice (path 0 with the automatic
-// LDS budget) takes it for views oblique to all three axes, whose slab boxes
-// would need the large budget: there the blocks read each voxel about once,
-// while the bundles' boxes overlap most.
+// LDS budget) takes it for views oblique to all three axes, where even the
+// best orientation copy needs wide slab boxes: there the blocks read each
+// voxel about once, while the bundles' boxes overlap most.
 static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single || p->mode != VR_MIP || !ctx->has_camera) return false;
     if (ctx->tune.path == 4) return true;
     if (ctx->tune.path != 0 || ctx->tune.lds_kib != 0 || ctx->tune.waves_per_group < 4) return false;
-    return vr_auto_box_kib(ctx->camd, ctx->vol, ctx->tune.packet_w,
-                           ctx->tune.packet_h * ctx->tune.waves_per_group) > 64;
+    double best = 1e300;
+    for (int o = 0; o < (ctx->vol.orients == 3 ? 3 : 1); ++o) {
+        VolDev v = ctx->vol;
+        apply_copy(v, o);
+        best = std::min(best, vr_box_estimate_kib(ctx->camd, v, ctx->tune.packet_w,
+                                                  ctx->tune.packet_h * ctx->tune.waves_per_group));
+    }
+    return best > 100.0;
 }
 
 // Automatic LDS budget of the slab path (tuning lds_kib = 0).  Two
@@ -233,7 +239,7 @@ static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
 // far slabs with direct gathers at that budget, so it gets one workgroup per
 // CU with 144 KiB.  The estimate: the box at slab thickness 2 near the far
 // face of the cube, for bundles spread over the viewport.
-int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh) {
+double vr_box_estimate_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh) {
     const double N[3] = {(double)v.nx, (double)v.ny, (double)v.nz};
     const int32_t L = 2;
     double worst = 0.0;
@@ -284,7 +290,11 @@ int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh
             worst = std::max(worst, ext[0] * ext[1] * ext[2] * 4.0 / 1024.0);
         }
     }
-    return worst > 100.0 ? 144 : 64;
+    return worst;
+}
+
+int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh) {
+    return vr_box_estimate_kib(c, v, bw, bh) > 100.0 ? 144 : 64;
 }
 
 static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s) {

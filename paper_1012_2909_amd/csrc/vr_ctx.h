@@ -45,6 +45,8 @@ int vr_check_params(vr_ctx *ctx, const vr_render_params *p);
 int vr_need_state(vr_ctx *ctx, bool lut_needed);
 vr::MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const vr::CamDev &cam);
 int32_t vr_auto_box_kib(const vr::CamDev &c, const vr::VolDev &v, int32_t bw, int32_t bh);
+// The estimate behind it: KiB of the widest far-side box at slab thickness 2.
+double vr_box_estimate_kib(const vr::CamDev &c, const vr::VolDev &v, int32_t bw, int32_t bh);
 // Pinned host staging of at least `bytes`; waits for the previous copy out of
 // it first.  NULL on failure.
 void *vr_stage(vr_ctx *ctx, size_t bytes);
