@@ -131,7 +131,14 @@ typedef struct {
     int32_t path;                 /* 0 auto, 1 direct gathers, 2 LDS-staged voxel boxes (one-brick layouts),
                                      3 direct gathers whose waves refill the lanes of finished rays with the
                                      next pixels of their workgroup's share of packets, once a ballot shows
-                                     at most half of the lanes live (one-brick layouts, waves_per_group <= 4) */
+                                     at most half of the lanes live (one-brick layouts, waves_per_group <= 4),
+                                     4 MIP in object order: blocks of the volume in LDS, one atomic maximum per
+                                     pixel and block (one-brick layouts, MIP only; needs the per-pixel ray
+                                     records vr_render_workspace_bytes counts, else renders as path 0).
+                                     Path 4 reads lds_kib 8..63 as 32x16x16 blocks (else 32x32x16),
+                                     waves_per_group 8 as 512 threads on the larger blocks, slab_max as the
+                                     blocks each workgroup walks along x.  Path 0 takes path 4 for MIP views
+                                     oblique to all three axes (lds_kib 0 and waves_per_group >= 4) */
     int32_t lds_kib;              /* LDS-staged path: voxel-box budget per workgroup, 8..144 KiB;
                                      0 = per view: 144 KiB for views oblique to all three axes, else 64 */
     int32_t slab_max;             /* LDS-staged path: thickest slab tried, 1..64 voxels */
@@ -204,9 +211,12 @@ int vr_set_camera(vr_ctx *ctx, const vr_camera *cam);
 
 /* ---- render ------------------------------------------------------------ */
 
-/* Workspace bytes vr_render needs for these params with the current camera
- * and volume (samples taken and transmittance checkpoints when
- * save_for_backward, else 0). */
+/* Workspace bytes vr_render needs for these params with the current camera,
+ * volume and launch shape: samples taken and transmittance checkpoints when
+ * save_for_backward; 64 bytes per pixel of ray records when the view is
+ * rendered in object order (MIP, path 4 or the automatic choice); else 0.
+ * With a smaller workspace an object-order view is rendered by the bundle
+ * kernels instead (the same image). */
 int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *params);
 
 /* Render the camera's viewport into out_dev: tile_h*tile_w*4 floats

@@ -449,3 +449,28 @@ def test_object_order_mip_matches_marching(R, storage, orient):
                 assert_bitexact_mip(R.render(mode="mip", filt="nearest").cpu().numpy(), o, f"object order {i}")
     finally:
         R.set_tuning(**base_t)
+
+
+def test_object_order_workspace_and_fallback(R, cube64):
+    """Path 4 asks for 64 bytes of ray record per pixel; without that
+    workspace the view is rendered by the bundle kernels, to the same image."""
+    from paper_1012_2909_amd import vr
+    lut = synth.lut_ramp()
+    cam = synth.orbit_camera(cube64.shape, seed=3, w=96, h=80)
+    base_t = R.get_tuning()
+    try:
+        R.load_volume(torch.from_numpy(cube64))
+        R.set_lut(lut)
+        R.set_camera(cam)
+        p = vr.params_struct(mode="mip")
+        R.set_tuning(**{**base_t, "path": 1})
+        assert int(vr.lib().vr_render_workspace_bytes(R.ctx, vr.C.byref(p))) == 0
+        ref = R.render(mode="mip").cpu().numpy()
+        R.set_tuning(**{**base_t, "path": 4})
+        assert int(vr.lib().vr_render_workspace_bytes(R.ctx, vr.C.byref(p))) == 96 * 80 * 64
+        out = torch.full(ref.shape, float("nan"), dtype=torch.float32, device="cuda")
+        assert vr.lib().vr_render(R.ctx, vr.C.byref(p), vr._ptr(out), None, 0, vr._stream()) == 0
+        assert np.array_equal(out.cpu().numpy(), ref)
+        assert np.array_equal(R.render(mode="mip").cpu().numpy(), ref)
+    finally:
+        R.set_tuning(**base_t)
