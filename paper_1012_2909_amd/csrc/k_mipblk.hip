@@ -15,8 +15,9 @@
 //   - copies the block's voxels (its corner indices and the +1 neighbours,
 //     (SX+1) x (SY+1) x (SZ+1)) from the padded x-fastest copy into LDS;
 //   - bounds the block's pixels by projecting the corners of the part of the
-//     cube its samples can occupy (a conservative rectangle; the whole tile
-//     when the region reaches behind the eye);
+//     cube its samples can occupy (the hull's bounding rectangle with a small
+//     margin; the whole tile when the region comes within a voxel of the
+//     eye's plane);
 //   - gives each lane one pixel of the rectangle: from the pixel's ray record
 //     (fixed-point start, step and sample count, computed once per frame) the
 //     lane finds the run [kb, ke) of samples inside the block -- a float
@@ -106,7 +107,7 @@ __device__ __forceinline__ void block_rect(const CamDev &c, const VolDev &v, con
         double sy = vx * c.u[0] + vy * c.u[1] + vz * c.u[2];
         if (c.kind == VR_PERSPECTIVE) {
             const double depth = vx * c.f[0] + vy * c.f[1] + vz * c.f[2];
-            if (depth <= 1e-9) whole = true;
+            if (depth < 1.0) whole = true;
             const double id = 1.0 / fmax(depth, 1e-9);
             sx *= id;
             sy *= id;
@@ -116,14 +117,18 @@ __device__ __forceinline__ void block_rect(const CamDev &c, const VolDev &v, con
         cmin = fmin(cmin, col); cmax = fmax(cmax, col);
         rmin = fmin(rmin, row); rmax = fmax(rmax, row);
     }
-    // the region lies in the cube, so its pixels are those of rays that hit
-    // the cube; clamp before converting (a region near the eye plane
-    // projects far away)
-    const double lim = 1e9;
-    x0 = whole ? 0 : (int32_t)fmax(floor(fmax(cmin, -lim)) - 1.0 - c.tile_x0, 0.0);
-    x1 = whole ? c.tile_w : (int32_t)fmin(ceil(fmin(cmax, lim)) + 2.0 - c.tile_x0, (double)c.tile_w);
-    y0 = whole ? 0 : (int32_t)fmax(floor(fmax(rmin, -lim)) - 1.0 - c.tile_y0, 0.0);
-    y1 = whole ? c.tile_h : (int32_t)fmin(ceil(fmin(rmax, lim)) + 2.0 - c.tile_y0, (double)c.tile_h);
+    // Pixel (col, row)'s ray meets the region iff (col, row) lies in the
+    // projected hull, whose bounding box this is.  The margin (1/20 pixel)
+    // covers the rounding of this projection and the drift of the samples'
+    // fixed-point positions from the exact ray (below 2e-6 voxel over the
+    // longest ray, under 1/200 pixel once the region is at least one voxel
+    // in front of the eye; nearer regions take the whole tile).  Clamp
+    // before converting.
+    const double lim = 1e9, m = 0.05;
+    x0 = whole ? 0 : (int32_t)fmax(floor(fmax(cmin - m, -lim)) - c.tile_x0, 0.0);
+    x1 = whole ? c.tile_w : (int32_t)fmin(floor(fmin(cmax + m, lim)) + 1.0 - c.tile_x0, (double)c.tile_w);
+    y0 = whole ? 0 : (int32_t)fmax(floor(fmax(rmin - m, -lim)) - c.tile_y0, 0.0);
+    y1 = whole ? c.tile_h : (int32_t)fmin(floor(fmin(rmax + m, lim)) + 1.0 - c.tile_y0, (double)c.tile_h);
     if (x1 < x0) x1 = x0;
     if (y1 < y0) y1 = y0;
 }

@@ -216,9 +216,10 @@ static bool use_compact_path(const vr_ctx *ctx) {
 
 // MIP in object order (path 4) on one-brick layouts; it keeps per-pixel ray
 // records in the workspace.  The automatic choice (path 0 with the automatic
-// LDS budget) takes it for views oblique to all three axes, where even the
-// best orientation copy needs wide slab boxes: there the blocks read each
-// voxel about once, while the bundles' boxes overlap most.
+// LDS budget) takes it for views whose far slab boxes, even in the best
+// orientation copy, would not fit the default 64 KiB budget (views oblique to
+// the axes): there the blocks read each voxel about once, while the
+// bundles' boxes overlap most.
 static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single || p->mode != VR_MIP || !ctx->has_camera) return false;
     if (ctx->tune.path == 4) return true;
@@ -230,7 +231,7 @@ static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
         best = std::min(best, vr_box_estimate_kib(ctx->camd, v, ctx->tune.packet_w,
                                                   ctx->tune.packet_h * ctx->tune.waves_per_group));
     }
-    return best > 100.0;
+    return best > 64.0;
 }
 
 // Automatic LDS budget of the slab path (tuning lds_kib = 0).  Two
