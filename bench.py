@@ -251,6 +251,7 @@ def main():
         "fps": {k: round(v, 2) for k, v in fps.items()},
         "gsamples_per_s": {k: round(v, 2) for k, v in gsps.items()},
         "samples_per_frame_mean": {n: int(np.mean(samples[n])) for n in modes},
+        "samples_per_angle": {n: [int(x) for x in samples[n]] for n in modes},
         "hbm_roofline_frac": {n: round(v, 4) for n, v in frac.items()},
         "ms_per_angle": {n: [round(float(np.mean([per_launch[n][k] for k in range(args.steps) if k % N_ANGLES == a])), 3)
                              for a in range(min(N_ANGLES, args.steps))] for n in modes},
