@@ -56,7 +56,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P, D, I64, I32 = C.c_void_p, C.c_double, C.c_int64, C.c_int32
         L.orc_render.argtypes = [P, I64, I64, I64, P, I32, D, D, P, P, P, I64, P, P, P, P, P, C.c_int]
-        L.orc_render_bricked.argtypes = [P, I64, I64, I64, P, I32, D, D, P, P, I64, I64, P, I64, P, P, C.c_int]
+        L.orc_render_bricked.argtypes = [P, I64, I64, I64, P, I32, D, D, P, P, I64, I64, P, I64, P, P, P, P,
+                                         C.c_int]
         L.orc_backward.argtypes = [P, I64, I64, I64, P, I32, D, D, P, P, P, P, P, C.c_int]
         L.orc_ray.argtypes = [P, I64, I64, P, P]
         L.orc_basis.argtypes = [P, P, P, P]
@@ -130,13 +131,15 @@ def render(vol, lut, cam, mode="composite", filt="trilinear", step=0.5, tau=0.99
 
 
 def render_bricked(vol, lut, cam, brick, mode="composite", filt="trilinear", step=0.5, tau=0.99,
-                   only_brick=-1, pixels=None, eps_stop=1e-5, eps_pos=1e-7, threads=0):
+                   only_brick=-1, pixels=None, eps_stop=1e-5, eps_t=1e-9, eps_pos=1e-7, threads=0):
     """Bricked render (per-brick partials, "over" in key order), or the partial
-    of one brick when only_brick >= 0."""
+    of one brick when only_brick >= 0.  Returns 'out', 'lo', 'hi' (candidate
+    interval over flipped stop and count decisions; brick-face ties are
+    flagged FLAG_BRICK but not widened) and 'flags'."""
     v, nx, ny, nz = _vol(vol)
     table = np.ascontiguousarray(lut.table, dtype=np.float32)
     c = _cam(cam)
-    p = _params(mode, filt, step, tau, eps_stop, 1e-9, eps_pos)
+    p = _params(mode, filt, step, tau, eps_stop, eps_t, eps_pos)
     ch = 1 if p.mode == 1 else 4
     if pixels is None:
         n = cam.tile[2] * cam.tile[3]
@@ -145,12 +148,16 @@ def render_bricked(vol, lut, cam, brick, mode="composite", filt="trilinear", ste
         pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
         n = pix.shape[0]
     out = np.zeros(n * ch)
+    lo = np.zeros(n * ch)
+    hi = np.zeros(n * ch)
     flags = np.zeros(n, np.int32)
     lib().orc_render_bricked(_ptr(v), nx, ny, nz, _ptr(table), table.shape[0], lut.vmin, lut.vmax,
                              C.byref(c), C.byref(p), int(brick), int(only_brick), _ptr(pix), n,
-                             _ptr(out), _ptr(flags), threads)
+                             _ptr(out), _ptr(lo), _ptr(hi), _ptr(flags), threads)
     shp = (cam.tile[3], cam.tile[2]) if pixels is None else (n,)
-    return {"out": out.reshape(shp + ((4,) if ch == 4 else ())), "flags": flags.reshape(shp)}
+    shp_c = shp + ((4,) if ch == 4 else ())
+    return {"out": out.reshape(shp_c), "lo": lo.reshape(shp_c), "hi": hi.reshape(shp_c),
+            "flags": flags.reshape(shp)}
 
 
 def backward(vol, lut, cam, grad_out, step=0.5, tau=0.99, threads=0):

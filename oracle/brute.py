@@ -91,8 +91,16 @@ def _lut(L, vmin, vmax, s):
 
 
 def render_pixel(V, L, vmin, vmax, eye, f, r, u, half_w, half_h, W, H, col, row,
-                 step=F(1, 2), tau=F(99, 100), mode="composite", filt="trilinear"):
-    """Exact render of one full-frame pixel (all arguments Fractions / ints)."""
+                 step=F(1, 2), tau=F(99, 100), mode="composite", filt="trilinear",
+                 count=None, cell_offset=None):
+    """Exact render of one full-frame pixel (all arguments Fractions / ints).
+
+    The two keyword arguments flip one discontinuous decision by hand, to
+    spell out a candidate outcome: `count` takes exactly that many samples
+    t0 + (k + 1/2) step, k < count, in place of the exit test t_k < t1;
+    `cell_offset` (three exact offsets) moves the position at which the
+    nearest voxel is looked up, e.g. (-1, 0, 0) to take the cell on the
+    other side of a face the sample lies on."""
     nz, ny, nx = len(V), len(V[0]), len(V[0][0])
     n = (nx, ny, nz)
     sx = (F(2) * (col + F(1, 2)) / W - 1) * half_w
@@ -110,10 +118,13 @@ def render_pixel(V, L, vmin, vmax, eye, f, r, u, half_w, half_h, W, H, col, row,
     C = [F(0)] * 3
     A = F(0)
     m = None
-    while t0 + (k + F(1, 2)) * step < t1:
+    while (t0 + (k + F(1, 2)) * step < t1) if count is None else k < count:
         t = t0 + (k + F(1, 2)) * step
         p = [o[a] + t * d[a] for a in range(3)]
-        s = _near(V, n, p) if filt == "nearest" else _tri(V, n, p)
+        if filt == "nearest":
+            s = _near(V, n, p if cell_offset is None else [p[a] + cell_offset[a] for a in range(3)])
+        else:
+            s = _tri(V, n, p)
         if mode == "mip":
             m = s if m is None or s > m else m
         else:

@@ -448,28 +448,115 @@ int64_t orc_brick_key(const orc_camera *cam, int64_t B, int64_t bx, int64_t by, 
     return key;
 }
 
-typedef struct { int64_t key, id; double c[4]; } part_t;
+/* One brick's share of a ray: its key and id, and its partial in three
+ * variants: [0] with the stop test A >= tau, [1] with tau - eps_stop, [2]
+ * with tau + eps_stop (the stop decision flipped either way). */
+typedef struct { int64_t key, id; double c[3][4]; int stopped[3]; } part_t;
 static int part_cmp(const void *x, const void *y) {
     const part_t *a = x, *b = y;
     if (a->key != b->key) return a->key < b->key ? -1 : 1;
     return a->id < b->id ? -1 : (a->id > b->id);
 }
 
+/* Per-brick partials of the first `count` samples of ray r, in ray order
+ * (bricks are convex, so each brick's samples are contiguous).  Returns the
+ * number of partials in *parts (grown as needed); ORs flags into *fl. */
+static int64_t brick_pass(const orc_scene *s, const orc_camera *cam, const orc_params *p, const ray_t *r,
+                          int64_t B, const int64_t nb[3], int64_t count, part_t **parts, int64_t *cap, int *fl) {
+    int ert = p->tau < 1.0;
+    double thr[3] = {p->tau, p->tau - p->eps_stop, p->tau + p->eps_stop};
+    int64_t np = 0, cur = -1;
+    part_t *pc = NULL;
+    for (int64_t k = 0; r->hit && k < count; ++k) {
+        double pos[3];
+        sample_pos(r, p->step, k, pos);
+        int64_t cell[3];
+        for (int a = 0; a < 3; ++a) {
+            cell[a] = brick_cell(pos[a], B, nb[a]);
+            double rel = pos[a] / (double)B - floor(pos[a] / (double)B);
+            if ((rel * B < p->eps_pos || (1.0 - rel) * B < p->eps_pos) && pos[a] > 0 &&
+                pos[a] < (double)(a == 0 ? s->nx : a == 1 ? s->ny : s->nz))
+                *fl |= FLAG_BRICK;
+        }
+        int64_t id = (cell[2] * nb[1] + cell[1]) * nb[0] + cell[0];
+        if (id != cur) {
+            if (np == *cap) { *cap *= 2; *parts = realloc(*parts, sizeof(part_t) * (size_t)*cap); }
+            pc = &(*parts)[np++];
+            pc->id = id;
+            pc->key = orc_brick_key(cam, B, cell[0], cell[1], cell[2]);
+            for (int v = 0; v < 3; ++v) {
+                pc->c[v][0] = pc->c[v][1] = pc->c[v][2] = pc->c[v][3] = 0.0;
+                if (p->mode == 1) pc->c[v][0] = -INFINITY;
+                pc->stopped[v] = 0;
+            }
+            cur = id;
+        }
+        double v, rgba[4];
+        if (p->filter == 1) {
+            double vl, vh;
+            int amb;
+            v = nearest(s, pos, p->eps_pos, &vl, &vh, &amb);
+            if (amb) *fl |= FLAG_CELL;
+        } else {
+            v = orc_trilinear(s, pos, NULL, NULL);
+        }
+        if (p->mode == 1) {
+            for (int w = 0; w < 3; ++w)
+                if (v > pc->c[w][0]) pc->c[w][0] = v;
+            continue;
+        }
+        orc_lut(s->lut, s->nlut, s->vmin, s->vmax, v, rgba, NULL, NULL, NULL);
+        for (int w = 0; w < 3; ++w) {
+            if (pc->stopped[w]) continue;
+            double A = pc->c[w][3], a = rgba[3];
+            for (int c = 0; c < 3; ++c) pc->c[w][c] += (1.0 - A) * a * rgba[c];
+            pc->c[w][3] = A + (1.0 - A) * a;
+            if (w == 0 && ert && fabs(pc->c[0][3] - p->tau) < p->eps_stop) *fl |= FLAG_STOP;
+            if (ert && pc->c[w][3] >= thr[w]) pc->stopped[w] = 1;
+        }
+    }
+    return np;
+}
+
+/* "Over" (composite) or maximum (MIP) of partials already in key order,
+ * taking variant sel[i] of partial i. */
+static void compose(const orc_params *p, const part_t *parts, int64_t np, const int *sel, double res[4]) {
+    res[0] = res[1] = res[2] = res[3] = 0.0;
+    if (p->mode == 1) res[0] = -INFINITY;
+    for (int64_t i = 0; i < np; ++i) {
+        const double *c = parts[i].c[sel ? sel[i] : 0];
+        if (p->mode == 1) {
+            if (c[0] > res[0]) res[0] = c[0];
+        } else {
+            double T = 1.0 - res[3];
+            for (int ch = 0; ch < 4; ++ch) res[ch] += T * c[ch];
+        }
+    }
+}
+
 /* Bricked render: per-brick partials (own early stop), then "over" in key
  * order.  Composite: 4 channels; MIP: max over partial maxima.
  * If only_brick >= 0, writes that brick's partial instead of the composite.
- * flags gets FLAG_BRICK when a sample lies within eps_pos of a brick face
- * and FLAG_STOP when a brick's stop decision is within eps_stop of tau. */
+ * flags gets FLAG_BRICK when a sample lies within eps_pos of a brick face,
+ * FLAG_STOP when a brick's stop decision is within eps_stop of tau and
+ * FLAG_COUNT when the ray's last-sample test is within its window.
+ * lo / hi (may be NULL) receive, per channel, the smallest and largest
+ * result over every combination of flipped decisions: the ray's sample
+ * count n_lo, n or n_hi, and per brick whose stop decision lies in the
+ * window, the stop at tau - eps_stop, tau or tau + eps_stop (a flipped
+ * decision of one brick changes what "over" does with every brick behind
+ * it, so the combinations are enumerated).  A brick-face tie (FLAG_BRICK)
+ * is flagged only: lo / hi do not cover it. */
 int orc_render_bricked(const float *vol, int64_t nx, int64_t ny, int64_t nz,
                        const float *lut, int32_t nlut, double vmin, double vmax,
                        const orc_camera *cam, const orc_params *p, int64_t B, int64_t only_brick,
-                       const int32_t *pix, int64_t npix, double *out, int32_t *flags, int nthreads) {
+                       const int32_t *pix, int64_t npix, double *out, double *lo, double *hi,
+                       int32_t *flags, int nthreads) {
     orc_scene s = {vol, nx, ny, nz, lut, nlut, vmin, vmax};
     int chans = p->mode == 1 ? 1 : 4;
     int64_t nb[3] = {(nx + B - 1) / B, (ny + B - 1) / B, (nz + B - 1) / B};
     if (!pix) npix = (int64_t)cam->tile_w * cam->tile_h;
     int nt = nthreads_of(nthreads);
-    int ert = p->tau < 1.0;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
     for (int64_t q = 0; q < npix; ++q) {
         int64_t x, y;
@@ -478,77 +565,71 @@ int orc_render_bricked(const float *vol, int64_t nx, int64_t ny, int64_t nz,
         ray_t r;
         ray_prepare(&s, cam, p, cam->tile_x0 + x, cam->tile_y0 + y, &r);
         int fl = 0;
-        int64_t cap = 16, np = 0;
-        part_t *parts = malloc(sizeof(part_t) * cap);
-        int64_t cur = -1;
-        part_t *pc = NULL;
-        int stopped = 0;
-        for (int64_t k = 0; r.hit && k < r.n; ++k) {
-            double pos[3];
-            sample_pos(&r, p->step, k, pos);
-            int64_t cell[3];
-            for (int a = 0; a < 3; ++a) {
-                cell[a] = brick_cell(pos[a], B, nb[a]);
-                double rel = pos[a] / (double)B - floor(pos[a] / (double)B);
-                if ((rel * B < p->eps_pos || (1.0 - rel) * B < p->eps_pos) && pos[a] > 0 &&
-                    pos[a] < (double)(a == 0 ? nx : a == 1 ? ny : nz))
-                    fl |= FLAG_BRICK;
-            }
-            int64_t id = (cell[2] * nb[1] + cell[1]) * nb[0] + cell[0];
-            if (id != cur) {
-                /* a new brick along the ray (bricks are convex, so its samples are contiguous) */
-                if (np == cap) { cap *= 2; parts = realloc(parts, sizeof(part_t) * cap); }
-                pc = &parts[np++];
-                pc->id = id;
-                pc->key = orc_brick_key(cam, B, cell[0], cell[1], cell[2]);
-                pc->c[0] = pc->c[1] = pc->c[2] = pc->c[3] = 0.0;
-                if (p->mode == 1) pc->c[0] = -INFINITY;
-                cur = id;
-                stopped = 0;
-            }
-            if (stopped) continue;
-            if (p->mode == 1) {
-                double v, vl, vh;
-                int amb = 0;
-                if (p->filter == 1) v = nearest(&s, pos, p->eps_pos, &vl, &vh, &amb);
-                else v = orc_trilinear(&s, pos, NULL, NULL);
-                if (amb) fl |= FLAG_CELL;
-                if (v > pc->c[0]) pc->c[0] = v;
-                continue;
-            }
-            double v, rgba[4];
-            if (p->filter == 1) {
-                double vl, vh;
-                int amb;
-                v = nearest(&s, pos, p->eps_pos, &vl, &vh, &amb);
-                if (amb) fl |= FLAG_CELL;
-            } else {
-                v = orc_trilinear(&s, pos, NULL, NULL);
-            }
-            orc_lut(lut, nlut, vmin, vmax, v, rgba, NULL, NULL, NULL);
-            double A = pc->c[3], a = rgba[3];
-            for (int c = 0; c < 3; ++c) pc->c[c] += (1.0 - A) * a * rgba[c];
-            pc->c[3] = A + (1.0 - A) * a;
-            if (ert && fabs(pc->c[3] - p->tau) < p->eps_stop) fl |= FLAG_STOP;
-            if (ert && pc->c[3] >= p->tau) stopped = 1;
-        }
-        double res[4] = {0, 0, 0, 0};
-        if (p->mode == 1) res[0] = -INFINITY;
+        if (r.hit && (r.n_lo != r.n || r.n_hi != r.n)) fl |= FLAG_COUNT;
+        int64_t cap = 16;
+        part_t *parts = malloc(sizeof(part_t) * (size_t)cap);
+        double res[4], rlo[4], rhi[4];
+        int64_t np = brick_pass(&s, cam, p, &r, B, nb, r.hit ? r.n : 0, &parts, &cap, &fl);
         if (only_brick >= 0) {
+            res[0] = res[1] = res[2] = res[3] = 0.0;
+            if (p->mode == 1) res[0] = -INFINITY;
             for (int64_t i = 0; i < np; ++i)
-                if (parts[i].id == only_brick) memcpy(res, parts[i].c, sizeof res);
+                if (parts[i].id == only_brick) memcpy(res, parts[i].c[0], sizeof res);
+            memcpy(rlo, res, sizeof res);
+            memcpy(rhi, res, sizeof res);
         } else {
             qsort(parts, (size_t)np, sizeof(part_t), part_cmp);
-            for (int64_t i = 0; i < np; ++i) {
-                if (p->mode == 1) {
-                    if (parts[i].c[0] > res[0]) res[0] = parts[i].c[0];
-                } else {
-                    double T = 1.0 - res[3];
-                    for (int c = 0; c < 4; ++c) res[c] += T * parts[i].c[c];
+            compose(p, parts, np, NULL, res);
+            memcpy(rlo, res, sizeof res);
+            memcpy(rhi, res, sizeof res);
+            /* candidate outcomes: every count variant, and per variant every
+             * choice of stop for the bricks whose stop lies in the window */
+            int64_t counts[3] = {r.n_lo, r.n, r.n_hi};
+            for (int cv = 0; cv < 3 && r.hit; ++cv) {
+                if (cv != 1 && counts[cv] == r.n) continue;
+                int64_t m = cv == 1 ? np : brick_pass(&s, cam, p, &r, B, nb, counts[cv], &parts, &cap, &fl);
+                if (cv != 1) qsort(parts, (size_t)m, sizeof(part_t), part_cmp);
+                int *sel = calloc((size_t)(m > 0 ? m : 1), sizeof(int));
+                int64_t amb[12], na = 0;
+                for (int64_t i = 0; i < m && p->mode != 1; ++i) {
+                    int differs = memcmp(parts[i].c[0], parts[i].c[1], sizeof parts[i].c[0]) != 0 ||
+                                  memcmp(parts[i].c[0], parts[i].c[2], sizeof parts[i].c[0]) != 0;
+                    if (differs && na < 12) amb[na++] = i;
                 }
+                int64_t combos = 1;
+                for (int64_t i = 0; i < na; ++i) combos *= 3;
+                for (int64_t cb = 0; cb < combos; ++cb) {
+                    int64_t t = cb;
+                    for (int64_t i = 0; i < na; ++i) { sel[amb[i]] = (int)(t % 3); t /= 3; }
+                    double alt[4];
+                    compose(p, parts, m, sel, alt);
+                    for (int c = 0; c < 4; ++c) {
+                        if (alt[c] < rlo[c]) rlo[c] = alt[c];
+                        if (alt[c] > rhi[c]) rhi[c] = alt[c];
+                    }
+                }
+                free(sel);
+            }
+            if (p->mode == 1 && p->filter == 1) {
+                /* nearest MIP: the cell candidates, as in the single pass */
+                double vlo = -INFINITY, vhi = -INFINITY;
+                for (int64_t k = 0; r.hit && k < r.n_hi; ++k) {
+                    double pos[3], vl, vh;
+                    int a;
+                    sample_pos(&r, p->step, k, pos);
+                    nearest(&s, pos, p->eps_pos, &vl, &vh, &a);
+                    if (k < r.n_lo && vl > vlo) vlo = vl;
+                    if (vh > vhi) vhi = vh;
+                }
+                if (vlo < rlo[0]) rlo[0] = vlo;
+                if (vhi > rhi[0]) rhi[0] = vhi;
             }
         }
-        for (int c = 0; c < chans; ++c) out[q * chans + c] = res[c];
+        for (int c = 0; c < chans; ++c) {
+            out[q * chans + c] = res[c];
+            if (lo) lo[q * chans + c] = rlo[c];
+            if (hi) hi[q * chans + c] = rhi[c];
+        }
         if (flags) flags[q] = fl;
         free(parts);
     }

@@ -25,13 +25,18 @@ class VolumeRenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, volume, table, renderer: "vr.Renderer", camera, vmin: float, vmax: float,
                 step: float = 0.5, ert: float = 0.99):
-        renderer.load_volume(volume.detach(), storage="f32", brick=0, orientations=1)
-        renderer.set_transfer_function(table.detach(), vmin, vmax)
+        vol, tab = volume.detach(), table.detach()
+        renderer.load_volume(vol, storage="f32", brick=0, orientations=1)
+        renderer.set_transfer_function(tab, vmin, vmax)
         renderer.set_camera(camera)
         img, ws = renderer.render("composite", "trilinear", step, ert, save=True)
         ctx.renderer = renderer
         ctx.ws = ws
         ctx.cfg = (step, ert)
+        # what the forward rendered from, so that the backward replays the
+        # same rays even if the renderer was used in between
+        ctx.scene = (vol, tab, camera, vmin, vmax)
+        ctx.generation = renderer.generation
         ctx.shapes = (volume.shape, table.shape)
         ctx.needs = (volume.requires_grad, table.requires_grad)
         return img
@@ -40,10 +45,16 @@ class VolumeRenderFn(torch.autograd.Function):
     def backward(ctx, grad_img):
         step, ert = ctx.cfg
         vshape, tshape = ctx.shapes
+        R = ctx.renderer
+        if R.generation != ctx.generation:
+            vol, tab, camera, vmin, vmax = ctx.scene
+            R.load_volume(vol, storage="f32", brick=0, orientations=1)
+            R.set_transfer_function(tab, vmin, vmax)
+            R.set_camera(camera)
         dev = grad_img.device
         gv = torch.zeros(vshape, dtype=torch.float32, device=dev) if ctx.needs[0] else None
         gl = torch.zeros(tshape, dtype=torch.float32, device=dev) if ctx.needs[1] else None
-        ctx.renderer.render_backward(grad_img.contiguous(), ctx.ws, gl, gv, step=step, ert=ert)
+        R.render_backward(grad_img.contiguous(), ctx.ws, gl, gv, step=step, ert=ert)
         return gv, gl, None, None, None, None, None, None
 
 

@@ -433,6 +433,7 @@ int vr_describe_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz, int32_t 
     ctx->vol = v;
     ctx->has_volume = true;
     ctx->vol_loaded = false;
+    ctx->vol_gen++;
     return ok(ctx);
 }
 

@@ -162,10 +162,14 @@ int vr_render_batch(vr_ctx *ctx, const vr_render_params *p, const vr_view *views
         if (e == hipSuccess) e = launch(s);
         return vr_dev_check(ctx, e, "batch");
     }
-    // graph: captured once per set of launch arguments, then replayed
+    // graph: captured once per set of launch arguments, then replayed.  The
+    // captured kernel argument holds the whole volume description (extents,
+    // pitches, storage type, copies), so the key holds the volume's
+    // generation: a volume described again at the same address (a caching
+    // allocator may hand it out again) is captured anew.
     std::vector<int64_t> key = {(int64_t)(intptr_t)ws, (int64_t)(intptr_t)luts, (int64_t)(intptr_t)ctx->vol.data,
-                                n_views, pl.total, lut_n, n_luts, p->mode, p->filter, a.trans, a.ert, groups,
-                                a.bw, a.bh, a.cap, a.lmax, direct, unroll};
+                                ctx->vol_gen, n_views, pl.total, lut_n, n_luts, p->mode, p->filter, a.trans, a.ert,
+                                groups, a.bw, a.bh, a.cap, a.lmax, direct, unroll};
     int64_t bits;
     std::memcpy(&bits, &p->step, 8);
     key.push_back(bits);

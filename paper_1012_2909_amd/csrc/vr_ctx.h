@@ -14,6 +14,7 @@ struct vr_ctx {
     bool has_volume = false;
     vr::VolDev vol{};
     bool vol_loaded = false;
+    int64_t vol_gen = 0;  // bumped by every vr_describe_volume: part of the batch graph's key
     // table
     bool has_lut = false;
     vr::LutDev lut{};

@@ -165,6 +165,9 @@ class Renderer:
         self.lut = None
         self.shape = None
         self.cam = None
+        # bumped by every call that changes what a render reads (volume,
+        # table, camera), so a caller can tell whether its state still holds
+        self.generation = 0
 
     def close(self):
         if self.ctx:
@@ -206,6 +209,7 @@ class Renderer:
         self.shape = (nz, ny, nx)
         self.brick = int(brick)
         self.storage_dtype = storage
+        self.generation += 1
         return self.storage
 
     def describe_volume(self, shape, storage="f32", brick=0, orientations=None):
@@ -223,10 +227,12 @@ class Renderer:
         self.shape = tuple(shape)
         self.brick = int(brick)
         self.storage_dtype = storage
+        self.generation += 1
 
     def load_slab(self, slab, z0):
         slab = slab.to(self.device, torch.float32).contiguous()
         self._check(lib().vr_load_slab(self.ctx, _ptr(slab), int(z0), int(slab.shape[0]), _stream()))
+        self.generation += 1
 
     # ---- table / camera ------------------------------------------------
     def set_transfer_function(self, table, vmin, vmax):
@@ -237,6 +243,7 @@ class Renderer:
                                                    float(vmin), float(vmax)))
         self.lut = table
         self.lut_range = (float(vmin), float(vmax))
+        self.generation += 1
 
     def set_lut(self, lut):
         self.set_transfer_function(lut.table, lut.vmin, lut.vmax)
@@ -245,6 +252,7 @@ class Renderer:
         c = camera_struct(cam)
         self._check(lib().vr_set_camera(self.ctx, C.byref(c)))
         self.cam = cam
+        self.generation += 1
 
     # ---- render --------------------------------------------------------
     def workspace_bytes(self, **kw):

@@ -103,6 +103,33 @@ def test_graph_replays_match_eager(R, cube):
     assert R.graph_captures() == n0 + 2
 
 
+def test_graph_recaptures_after_a_new_volume(R, cube):
+    """A captured graph holds the volume description in its kernel argument.
+    Loading another cube (other shape and storage type, possibly at the same
+    address) must capture again, and the replay must equal the eager images
+    of the new cube."""
+    R.load_volume(torch.from_numpy(cube))
+    cams, luts = _views(13, 4)
+    packed = R.stack_luts(luts)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        R.render_batch(cams, packed, use_graph=True, stream=s)
+    s.synchronize()
+    n0 = R.graph_captures()
+    small = np.ascontiguousarray(cube[:40, :44, :52])
+    old_ptr = R.storage.data_ptr()
+    R.load_volume(torch.from_numpy(small), storage="f16")
+    log(f"storage reused at the same address: {R.storage.data_ptr() == old_ptr}")
+    with torch.cuda.stream(s):
+        got = R.render_batch(cams, packed, use_graph=True, stream=s)
+    s.synchronize()
+    assert R.graph_captures() == n0 + 1
+    eager = _one_by_one(R, cams, luts)
+    torch.cuda.synchronize()
+    for i, (g, e) in enumerate(zip(got, eager)):
+        assert np.array_equal(g.cpu().numpy(), e), f"view {i}"
+
+
 def test_five_by_five_wall_in_one_batch(R, cube):
     """The 25 panels of a tiled frame rendered as one batch stitch into the
     full-frame render."""

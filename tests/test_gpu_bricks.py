@@ -70,11 +70,36 @@ def test_bricked_with_early_stop_matches_oracle(R, brick, cam_name):
     _setup(R, vol, lut, cam, brick)
     img = R.render_bricked().cpu().numpy()
     res = oracle.render_bricked(vol, lut, cam, brick, eps_stop=2e-5)
-    ok = res["flags"] == 0
-    err = np.abs(img - res["out"])[ok].max()
-    log(f"bricked ERT max err {err:.2e} over {ok.sum()} unflagged px ({(~ok).sum()} flagged)")
-    assert err <= TOL_COMPOSITE
-    assert ok.mean() > 0.9
+    # flagged pixels are checked against the candidate interval (flipped
+    # stop and count decisions); only brick-face ties are left out
+    face = (res["flags"] & oracle.FLAG_BRICK) != 0
+    assert face.sum() <= 2
+    keep = ~face
+    assert_accept(img[keep], {k: v[keep] for k, v in res.items()}, TOL_COMPOSITE,
+                  what=f"bricked ERT brick={brick} cam={cam_name}")
+
+
+@pytest.mark.parametrize("brick", [5, 7, 16])
+@pytest.mark.parametrize("eye,target", [((21.3, 17.7, 29.1), (60.0, 5.0, 40.0)),
+                                        ((35.6, 8.4, 12.2), (-8.0, 30.0, 50.0))])
+def test_bricked_eye_inside_grid(R, brick, eye, target):
+    """Perspective eye inside the cube, so inside the brick grid: the
+    Manhattan order from the eye's cell must still be front to back.  Without
+    the early stop the bricked render equals the single pass (1e-6) and the
+    oracle's bricked render; MIP is bit-identical to the single pass."""
+    log(f"case: bricked eye inside brick={brick} eye={eye}")
+    shape = (60, 36, 46)
+    vol = synth.make_cube(synth.CubeSpec(shape, 10, seed=3, fwhm_z=(4.0, 20.0)))
+    lut = synth.lut_ramp(alpha_scale=1 / 8)
+    cam = synth.Camera(synth.PERSPECTIVE, eye, target, (0.0, -1.0, 0.0), fovy_deg=100.0, full_w=96, full_h=72)
+    _setup(R, vol, lut, cam, brick)
+    br = R.render_bricked(ert=1.0).cpu().numpy()
+    one = R.render(ert=1.0).cpu().numpy()
+    assert np.abs(br - one).max() <= 1e-6
+    assert_accept(br, oracle.render_bricked(vol, lut, cam, brick, tau=1.0), TOL_COMPOSITE,
+                  what=f"bricked eye inside brick={brick}")
+    brm = R.render_bricked(mode="mip", ert=1.0).cpu().numpy()
+    assert np.array_equal(brm, R.render(mode="mip").cpu().numpy())
 
 
 @pytest.mark.parametrize("mode,filt", [("composite", "trilinear"), ("mip", "trilinear"), ("mip", "nearest")])

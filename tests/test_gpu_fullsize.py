@@ -117,7 +117,9 @@ def test_64gib_bricked_9600x5400_sampled(R, cube64, storage):
     frame = synth.orbit_camera(spec.shape, seed=3, w=9600, h=5400)
     tiles = synth.tiles_5x5(frame)
     tol = TOL_COMPOSITE if storage == "f32" else TOL_LOWP
-    for t in (0, 12, 18):
+    # tiles that see the cube: 6 holds its silhouette's edge, 12 its centre,
+    # 18 a partly covered panel (the frame's corner panels see nothing)
+    for t in (6, 12, 18):
         cam = tiles[t]
         R.set_camera(cam)
         # MIP of rounded storage has no stated bar: FP32 storage only
@@ -125,16 +127,19 @@ def test_64gib_bricked_9600x5400_sampled(R, cube64, storage):
             img = R.render_bricked(mode=mode).cpu().numpy()
             pix = _pixels(img, 300, 300 + t)
             got = img[pix[:, 1], pix[:, 0]]
-            res = oracle.render_bricked(cube64, lut, cam, 256, mode=mode, pixels=pix)
-            ok_px = res["flags"] == 0
-            ref = res["out"]
-            err = np.abs(got[ok_px].astype(np.float64) - ref[ok_px])
-            fin = np.isfinite(ref[ok_px])
-            err = np.where(fin, err, np.where(got[ok_px] == ref[ok_px], 0.0, np.inf))
+            res = oracle.render_bricked(cube64, lut, cam, 256, mode=mode, pixels=pix, eps_stop=2e-5)
+            hits = int((got[:, 3] > 0).sum()) if mode == "composite" else int(np.isfinite(got).sum())
+            assert hits >= len(pix) // 5, f"tile {t}: only {hits} of {len(pix)} sampled pixels see the cube"
+            # brick-face ties (a sample within 1e-7 voxel of a brick face, which
+            # the two sides may assign to different bricks) are the only
+            # flagged pixels the candidate interval does not cover
+            face = (res["flags"] & oracle.FLAG_BRICK) != 0
+            assert face.sum() <= 2
+            keep = ~face
+            sub = {k: v[keep] for k, v in res.items()}
             bound = tol if mode == "composite" else mip_tol(vmax)
-            log(f"64 GiB {storage} tile {t} {mode}: {len(pix)} px, {int((~ok_px).sum())} flagged, "
-                f"max err {float(np.max(err)) if err.size else 0.0:.3e}")
-            assert (err <= bound).all()
+            assert_accept(got[keep], sub, bound,
+                          what=f"64 GiB {storage} tile {t} {mode} ({len(pix)} px, {hits} hit)")
 
 
 def test_512mib_f16_batch_of_64_views_graph_sampled(R):

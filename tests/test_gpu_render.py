@@ -312,22 +312,29 @@ def test_low_precision_storage(R, storage):
     deq = _dequant(vol, storage)
     # arithmetic error alone: against the oracle on the rounded cube
     assert_accept(img, oracle.render(deq, lut, cam, eps_stop=2e-5), TOL_COMPOSITE, what=f"{storage} vs rounded cube")
-    # total error against the original FP32 cube
-    res = oracle.render(vol, lut, cam, eps_stop=2e-5)
-    ok_mask_err = np.abs(img - res["out"])
-    flagged = res["flags"] != 0
-    mx = float(ok_mask_err[~flagged].max())
-    log(f"{storage} vs fp32 cube: max abs {mx:.3e}")
-    if storage == "f16":
-        assert mx <= TOL_LOWP
-    else:
-        # BF16 keeps 8 mantissa bits: a bright voxel (|v| in [8,16)) is rounded
-        # by up to 2^-5, i.e. 2.4e-3 of the table's range; report, bound loosely
-        assert mx <= 4 * TOL_LOWP
     # MIP nearest on rounded storage is bit-exact against the rounded cube
     R.set_camera(cam)
     mipn = R.render(mode="mip", filt="nearest").cpu().numpy()
     assert_bitexact_mip(mipn, oracle.render(deq, lut, cam, mode="mip", filt="nearest"), f"{storage} nearest MIP")
+    # total error against the original FP32 cube: arithmetic (above, <= 1e-5)
+    # plus the effect of rounding the stored values, which the storage format
+    # fixes, not the renderer: the oracle on the rounded cube against the
+    # oracle on the FP32 cube measures that part alone
+    res = oracle.render(vol, lut, cam, eps_stop=2e-5)
+    ref_q = oracle.render(deq, lut, cam, eps_stop=2e-5)
+    flagged = (res["flags"] != 0) | (ref_q["flags"] != 0)
+    mx = float(np.abs(img - res["out"])[~flagged].max())
+    quant = float(np.abs(ref_q["out"] - res["out"])[~flagged].max())
+    log(f"{storage} vs fp32 cube: max abs {mx:.3e} (rounding of the stored values alone: {quant:.3e}, "
+        f"bar {TOL_LOWP})")
+    assert mx <= quant + TOL_COMPOSITE
+    if storage == "bf16" and mx > TOL_LOWP:
+        # BF16 keeps 8 significant bits: a voxel near the table's top (|v| in
+        # [8, 16)) moves by up to 2^-5 = 0.031, i.e. up to 2.4e-3 in alpha
+        # through the ramp's slope 1/13, and a ray whose transmittance mass
+        # sits on such samples sums that error in both alpha and colour
+        pytest.xfail(f"BF16 storage misses the 2e-3 bar against the FP32 cube: {mx:.2e}")
+    assert mx <= TOL_LOWP
 
 
 # ---------------------------------------------------------------------------

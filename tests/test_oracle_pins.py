@@ -527,3 +527,159 @@ def test_brick_partials_are_column_segments(tau):
     for bz in range(4):                       # +z view: keys increase with bz
         ref = ref + (1 - ref[..., 3:4]) * parts[bz]
     assert np.abs(full - ref).max() < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# candidate outcomes, pinned one decision at a time: each case builds an exact
+# tie of one discontinuous decision (the exit test, the stop test, the nearest
+# cell) on a single axis-aligned ray, and the oracle's lo / hi must equal the
+# exact-rational render with that one decision flipped by hand
+# ----------------------------------------------------------------------------
+def _axis_ray_camera(x, y):
+    """Orthographic 1x1 frame whose single ray starts at (x, y, -1) and runs
+    along +z (sx = sy = 0, so the origin is the eye exactly)."""
+    return synth.Camera(synth.ORTHO, (x, y, -1.0), (x, y, 0.0), (0.0, -1.0, 0.0),
+                        half_w=0.5, half_h=0.5, full_w=1, full_h=1)
+
+
+_AXIS_BASIS = ((F(0), F(0), F(1)), (F(1), F(0), F(0)), (F(0), F(-1), F(0)))
+
+
+def _brute_axis(vol, lut, x, y, **kw):
+    f, r, u = _AXIS_BASIS
+    return brute.render_pixel(brute.to_frac_volume(vol), brute.to_frac_lut(lut.table), F(lut.vmin), F(lut.vmax),
+                              [F(x), F(y), F(-1)], f, r, u, F(1, 2), F(1, 2), 1, 1, 0, 0, **kw)
+
+
+def _frac_close(got, ref, tol=1e-15):
+    ref = np.atleast_1d(np.array([float(v) for v in np.atleast_1d(ref)]))
+    return np.abs(np.atleast_1d(got) - ref).max() <= tol
+
+
+def test_count_candidates_flip_the_exit_test():
+    """Samples at z = 0.5, 1.5, 2.5, 3.5 of a 4-deep column (t0 = 1, t1 = 5,
+    step 1).  A window of 0.55 around t1 reaches the last sample inside
+    (t = 4.5) and the first one outside (t = 5.5): lo is the render that drops
+    the last sample (3 samples), hi the render that takes one more (5), out
+    the render of the 4 of the definition."""
+    vol = np.array([-2.0, 5.0, 1.5, 7.25], np.float32).reshape(4, 1, 1)
+    lut = synth.lut_dyadic([[0, 0, 0, 0], [1.0, 0.5, 0.25, 0.5]], -4.0, 12.0)
+    cam = _axis_ray_camera(0.5, 0.5)
+    eps_t = 0.11   # window = eps_t * |t1| = 0.55 > 0.5
+    res = oracle.render(vol, lut, cam, step=1.0, tau=1.0, eps_t=eps_t)
+    assert res["flags"][0, 0] == oracle.FLAG_COUNT and res["taken"][0, 0] == 4
+    for key, count in (("out", None), ("lo", 3), ("hi", 5)):
+        ref = _brute_axis(vol, lut, 0.5, 0.5, step=F(1), tau=F(1), count=count)
+        assert _frac_close(res[key][0, 0], ref), key
+    # the candidates differ from each other (so an off-by-one is visible)
+    assert len({tuple(res[k][0, 0]) for k in ("out", "lo", "hi")}) == 3
+    mip = oracle.render(vol, lut, cam, mode="mip", step=1.0, eps_t=eps_t)
+    for key, count in (("out", None), ("lo", 3), ("hi", 5)):
+        assert mip[key][0, 0] == float(_brute_axis(vol, lut, 0.5, 0.5, step=F(1), mode="mip", count=count)), key
+    assert mip["lo"][0, 0] == 5.0 and mip["out"][0, 0] == 7.25
+    # outside the window nothing is flagged and all three agree
+    tight = oracle.render(vol, lut, cam, step=1.0, tau=1.0, eps_t=0.09)
+    assert tight["flags"][0, 0] == 0
+    assert np.array_equal(tight["lo"], tight["out"]) and np.array_equal(tight["hi"], tight["out"])
+
+
+@pytest.mark.parametrize("side", [-1, 1])
+def test_stop_candidates_flip_the_stop_test(side):
+    """Constant alpha 1/2 (table rgba = s on [0, 1], cube of 0.5): A runs 1/2,
+    3/4, 7/8 exactly.  With tau = 3/4 -/+ eps/2 the threshold lies inside the
+    window around A = 3/4: lo is the render that stops at tau - eps, hi the
+    one that stops at tau + eps (the exact render with the stop test moved),
+    and the closed form C = A/2, A = 1 - 2^-n holds for each."""
+    vol = np.full((8, 1, 1), 0.5, np.float32)
+    lut = synth.lut_dyadic([[0, 0, 0, 0], [1, 1, 1, 1]], 0.0, 1.0)
+    cam = _axis_ray_camera(0.5, 0.5)
+    eps = 1e-3
+    tau = 0.75 + side * eps / 2
+    res = oracle.render(vol, lut, cam, step=1.0, tau=tau, eps_stop=eps)
+    assert res["flags"][0, 0] & oracle.FLAG_STOP
+    n_main = 2 if side < 0 else 3
+    for key, t, n in (("out", F(tau), n_main), ("lo", F(tau) - F(eps), 2), ("hi", F(tau) + F(eps), 3)):
+        ref = _brute_axis(vol, lut, 0.5, 0.5, step=F(1), tau=t)
+        assert _frac_close(res[key][0, 0], ref), key
+        A = 1.0 - 0.5 ** n
+        assert np.array_equal(res[key][0, 0], [A / 2, A / 2, A / 2, A]), key
+    assert res["taken"][0, 0] == n_main
+
+
+def test_cell_candidates_flip_the_nearest_cell():
+    """Nearest MIP along z through x = 3 exactly (the face between voxels 2
+    and 3) and through x = 3 - 2^-30 (just inside voxel 2): the candidates
+    are the two voxels on either side of that face and no other.  Voxels one
+    further away hold the extremes (10 and -5), so a window that reached them
+    would show."""
+    vals = np.array([0.0, 10.0, 1.0, 2.0, -5.0, 7.0], np.float32)
+    vol = vals.reshape(1, 1, 6)
+    lut = synth.lut_ramp()
+    for x, main, other, off in ((3.0, 2.0, 1.0, -1), (3.0 - 2.0 ** -30, 1.0, 2.0, 1)):
+        cam = _axis_ray_camera(x, 0.5)
+        res = oracle.render(vol, lut, cam, mode="mip", filt="nearest")
+        assert res["flags"][0, 0] == oracle.FLAG_CELL
+        ref_main = _brute_axis(vol, lut, x, 0.5, mode="mip", filt="nearest")
+        ref_flip = _brute_axis(vol, lut, x, 0.5, mode="mip", filt="nearest", cell_offset=(F(off), F(0), F(0)))
+        assert (float(ref_main), float(ref_flip)) == (main, other)
+        assert res["out"][0, 0] == main
+        assert res["lo"][0, 0] == min(main, other) and res["hi"][0, 0] == max(main, other)
+
+
+# ----------------------------------------------------------------------------
+# bricks with the eye inside the brick grid
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("B", [5, 7, 16])
+@pytest.mark.parametrize("eye,target", [((7.3, 6.7, 11.1), (30.0, 2.0, 18.0)),
+                                        ((12.6, 3.4, 4.2), (-8.0, 12.0, 16.0))])
+def test_bricked_equals_single_pass_eye_inside_grid(B, eye, target):
+    """Perspective eye inside the cube (so inside the brick grid, off every
+    brick face): rays leave the eye's brick in all directions, and the
+    Manhattan key from the eye's cell must still order the partials front to
+    back.  Without early stop the bricked render equals the single pass."""
+    shape = (20, 14, 17)
+    vol = synth.make_cube(synth.CubeSpec(shape, 6, seed=22))
+    lut = synth.lut_ramp(alpha_scale=1 / 4)
+    cam = synth.Camera(synth.PERSPECTIVE, eye, target, (0.0, -1.0, 0.0), fovy_deg=100.0, full_w=40, full_h=30)
+    one = oracle.render(vol, lut, cam, tau=1.0)["out"]
+    br = oracle.render_bricked(vol, lut, cam, B, tau=1.0)["out"]
+    assert one[..., 3].min() > 0.05          # every ray composites several bricks
+    assert np.abs(one - br).max() <= 1e-12
+
+
+def test_bricked_stop_candidates_cover_every_combination():
+    """Two bricks of 4 samples each along one axis ray, constant alpha 1/2,
+    tau = 3/4 + eps/2: each brick stops after 3 samples (A = 7/8), or after 2
+    with the stop decision flipped (A = 3/4).  The "over" of the two partials
+    is then 1 - 2^-(n0+n1) with n0, n1 in {2, 3}: the candidate interval
+    spans both bricks flipped (1 - 2^-4) to neither (1 - 2^-6), with C = A/2
+    throughout."""
+    vol = np.full((8, 1, 1), 0.5, np.float32)
+    lut = synth.lut_dyadic([[0, 0, 0, 0], [1, 1, 1, 1]], 0.0, 1.0)
+    cam = _axis_ray_camera(0.5, 0.5)
+    eps = 1e-3
+    res = oracle.render_bricked(vol, lut, cam, 4, step=1.0, tau=0.75 + eps / 2, eps_stop=eps)
+    assert res["flags"][0, 0] & oracle.FLAG_STOP
+    for key, n in (("out", 6), ("lo", 4), ("hi", 6)):
+        A = 1.0 - 0.5 ** n
+        assert np.array_equal(res[key][0, 0], [A / 2, A / 2, A / 2, A]), key
+    # without a tie in the window the interval collapses onto the result
+    res = oracle.render_bricked(vol, lut, cam, 4, step=1.0, tau=0.8, eps_stop=eps)
+    assert res["flags"][0, 0] == 0
+    assert np.array_equal(res["lo"], res["out"]) and np.array_equal(res["hi"], res["out"])
+
+
+def test_bricked_candidates_bracket_the_result():
+    """On a noisy cube with early stop, every bricked result lies inside its
+    candidate interval, unflagged pixels have a collapsed interval, and the
+    flagged ones include stop ties."""
+    shape = (24, 20, 22)
+    vol = synth.make_cube(synth.CubeSpec(shape, 8, seed=23))
+    lut = synth.lut_ramp(alpha_scale=0.5)
+    cam = synth.orbit_camera(shape, seed=7, w=48, h=40)
+    res = oracle.render_bricked(vol, lut, cam, 7, eps_stop=1e-3)
+    o, lo, hi, fl = res["out"], res["lo"], res["hi"], res["flags"]
+    assert (lo <= o + 1e-15).all() and (o <= hi + 1e-15).all()
+    clean = fl == 0
+    assert np.array_equal(lo[clean], o[clean]) and np.array_equal(hi[clean], o[clean])
+    assert ((fl & oracle.FLAG_STOP) != 0).any()
