@@ -202,7 +202,11 @@ int vr_load_slab(vr_ctx *ctx, const float *src_dev, int64_t z0, int64_t nz_slab,
 /* ---- transfer function (section 2: the colour map) --------------------- */
 
 /* n straight-RGBA float32 entries (n*4 floats on the device, n in [2, 1024])
- * over [vmin, vmax] (vmax > vmin).  Borrowed: must stay valid while used. */
+ * over [vmin, vmax] (vmax > vmin).  Borrowed: must stay valid while used.
+ * The call reads the table back once (a blocking copy of n*16 bytes, so the
+ * entries must be in place when it is made) to find its largest opacity:
+ * that bounds how early a composite ray can stop and picks the kernel of
+ * vr_render's automatic path; the images do not depend on it. */
 int vr_set_transfer_function(vr_ctx *ctx, const float *rgba_dev, int32_t n, float vmin, float vmax);
 
 /* ---- camera (section 3: same orientation, user-defined output size) ----- */
@@ -274,6 +278,77 @@ int vr_composite_bricks(vr_ctx *ctx, const vr_render_params *params, const vr_pa
 int vr_render_backward(vr_ctx *ctx, const vr_render_params *params, const float *grad_out_dev,
                        const void *workspace_dev, int64_t ws_bytes, float *grad_lut_dev,
                        float *grad_vol_dev, void *stream);
+
+/* ---- depth and catalogue overlay (section 2: a source finder's catalogue
+ *      of detected sources, each a bounding cube, drawn as wireframe boxes
+ *      over the rendering and following the view) ----------------------- */
+
+/* One catalogue entry: the axis-aligned box [lo, hi] in voxel coordinates of
+ * the cube (world units; a source covering voxels i0..i1 along an axis spans
+ * [i0, i1 + 1]) and its straight RGBA colour (alpha: how strongly it is
+ * drawn over the image). */
+typedef struct {
+    float lo[3], hi[3];
+    float rgba[4];
+} vr_box;
+
+/* Per-pixel depth of the current view, tile_h*tile_w floats: the ray
+ * parameter t (voxels from the ray's origin) of
+ *  - composite: the first sample after which the accumulated opacity A
+ *    reaches `level` (in (0, 1]), among the samples the render takes (the
+ *    early stop included), with the render's own FP32 arithmetic;
+ *  - MIP: the first sample whose value equals the ray's maximum;
+ * +inf where there is no such sample (a miss, or A never reaches level).
+ * One-brick layouts only (EUNSUPPORTED for bricked ones); the params are
+ * those of the render the depth belongs to (save_for_backward ignored). */
+int vr_render_depth(vr_ctx *ctx, const vr_render_params *params, float level, float *depth_dev, void *stream);
+
+/* Draw n catalogue boxes (boxes_dev: n vr_box on the device) as wireframes
+ * over image_dev, the current view's premultiplied RGBA tile (tile_h*tile_w*4
+ * floats, modified in place).  A pixel is covered by an edge when its centre
+ * lies within half_width pixels (in (0, 64]) of the edge's projection (the
+ * part in front of the near plane, 1e-3 voxel before a perspective eye);
+ * the edge's depth there is the ray distance of its 3D point under the
+ * projected segment's point nearest the centre, and the edge is visible
+ * when that depth is at most depth_dev's value at the pixel (depth_dev NULL:
+ * every edge is visible; pass vr_render_depth's output to hide edges behind
+ * the rendered emission).  Each pixel takes the colour of the nearest
+ * visible covering box (ties: the lower index) and becomes
+ * rgba.a * (r, g, b, 1) + (1 - a) * pixel. */
+int vr_overlay_boxes(vr_ctx *ctx, const vr_box *boxes_dev, int32_t n, float half_width, const float *depth_dev,
+                     float *image_dev, void *stream);
+
+/* ---- display pyramid and pyramidal tiled TIFF (section 3: the static
+ *      high-resolution render is stored as a TIFF and converted to the
+ *      pyramidal tiled TIFF an image server streams to the tiled wall) ---- */
+
+/* Bytes of the display pyramid of a w x h image with square tiles of `tile`
+ * pixels (a multiple of 16 in [16, 4096]): level 0 is w x h, level l+1 is
+ * ceil(w_l/2) x ceil(h_l/2), and the levels stop at the first one whose
+ * sides both fit one tile; every level is RGBA8 (4 bytes per pixel, rows
+ * packed), the levels stored one after the other.  *levels_out (may be
+ * NULL) gets their number.  Pure host function; < 0 on invalid sizes. */
+int64_t vr_pyramid_bytes(int32_t w, int32_t h, int32_t tile, int32_t *levels_out);
+
+/* Build the pyramid of a premultiplied RGBA float image (rgba_dev: h*w*4
+ * floats, 16-byte aligned) into dst_dev (vr_pyramid_bytes bytes, 4-byte
+ * aligned).  Level 0 per channel: floor(clamp(v, 0, 1) * 255 + 1/2), NaN
+ * as 0, computed exactly; level l+1 pixel (x, y): per channel the rounded
+ * mean (s + n/2) / n (integer division) of the n <= 4 pixels (2x + a,
+ * 2y + b), a, b in {0, 1}, that exist in level l. */
+int vr_build_pyramid(vr_ctx *ctx, const float *rgba_dev, int32_t w, int32_t h, int32_t tile, uint8_t *dst_dev,
+                     int64_t dst_bytes, void *stream);
+
+/* Write a pyramid (a host copy of vr_build_pyramid's output for the same w,
+ * h, tile) to `path` as a pyramidal tiled TIFF: one image file directory per
+ * level, chained from full resolution down (NewSubfileType 1 on the reduced
+ * levels), tile x tile tiles (zero beyond the image), 8-bit RGBA with
+ * associated alpha (the render's premultiplied colour), uncompressed.
+ * bigtiff: 0 writes classic TIFF unless the file reaches 4 GiB (then
+ * BigTIFF), 1 always BigTIFF.  Host only (no context); errors are reported
+ * through vr_last_error(NULL). */
+int vr_write_pyramid_tiff(const char *path, const uint8_t *pyramid_host, int32_t w, int32_t h, int32_t tile,
+                          int32_t bigtiff);
 
 /* ---- batches (section 3: many viewports / display tiles at once) --------- */
 

@@ -67,6 +67,8 @@ def lib():
         L.orc_brick_key.argtypes = [P, I64, I64, I64, I64]
         L.orc_brick_key.restype = I64
         L.orc_ray_interval.argtypes = [P, I64, I64, I64, P, P, I64, I64, P, P, P, P, P]
+        L.orc_depth.argtypes = [P, I64, I64, I64, P, I32, D, D, P, P, D, D, P, I64, P, P, P, P, C.c_int]
+        L.orc_overlay.argtypes = [P, P, I64, D, D, P, D, P, P, C.c_int]
         _lib = L
     return _lib
 
@@ -158,6 +160,46 @@ def render_bricked(vol, lut, cam, brick, mode="composite", filt="trilinear", ste
     shp_c = shp + ((4,) if ch == 4 else ())
     return {"out": out.reshape(shp_c), "lo": lo.reshape(shp_c), "hi": hi.reshape(shp_c),
             "flags": flags.reshape(shp)}
+
+
+def depth(vol, lut, cam, mode="composite", filt="trilinear", step=0.5, tau=0.99, level=0.5, pixels=None,
+          eps_stop=1e-5, eps_t=1e-9, eps_pos=1e-7, eps_val=0.0, threads=0):
+    """Per-pixel depth (ray parameter t, +inf for none): composite, the first
+    sample after which A reaches `level`; MIP, the first sample equal to the
+    maximum.  Returns 'out', 'lo', 'hi' (candidate depths over flipped
+    decisions) and 'flags'."""
+    v, nx, ny, nz = _vol(vol)
+    table = np.ascontiguousarray(lut.table, dtype=np.float32)
+    c = _cam(cam)
+    p = _params(mode, filt, step, tau, eps_stop, eps_t, eps_pos)
+    if pixels is None:
+        n = cam.tile[2] * cam.tile[3]
+        pix = None
+        shp = (cam.tile[3], cam.tile[2])
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int32).reshape(-1, 2)
+        n = pix.shape[0]
+        shp = (n,)
+    out, lo, hi = np.zeros(n), np.zeros(n), np.zeros(n)
+    flags = np.zeros(n, np.int32)
+    lib().orc_depth(_ptr(v), nx, ny, nz, _ptr(table), table.shape[0], lut.vmin, lut.vmax, C.byref(c),
+                    C.byref(p), float(level), float(eps_val), _ptr(pix), n, _ptr(out), _ptr(lo), _ptr(hi),
+                    _ptr(flags), threads)
+    return {"out": out.reshape(shp), "lo": lo.reshape(shp), "hi": hi.reshape(shp), "flags": flags.reshape(shp)}
+
+
+def overlay(cam, boxes, image, half_width=0.75, near=1e-3, depth=None, eps=1e-9, threads=0):
+    """Wireframe boxes over a premultiplied RGBA tile.  boxes: (n, 10) =
+    lo xyz, hi xyz, straight RGBA; image: (h, w, 4), not modified; depth:
+    (h, w) float32 or None.  Returns (image with the overlay (FP64), flags)."""
+    c = _cam(cam)
+    b = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 10)
+    img = np.array(image, dtype=np.float64, copy=True).reshape(cam.tile[3], cam.tile[2], 4)
+    d = None if depth is None else np.ascontiguousarray(depth, dtype=np.float32).reshape(cam.tile[3], cam.tile[2])
+    flags = np.zeros((cam.tile[3], cam.tile[2]), np.int32)
+    lib().orc_overlay(C.byref(c), _ptr(b), b.shape[0], float(half_width), float(near), _ptr(d), float(eps),
+                      _ptr(img), _ptr(flags), threads)
+    return img, flags
 
 
 def backward(vol, lut, cam, grad_out, step=0.5, tau=0.99, threads=0):

@@ -421,6 +421,268 @@ int orc_ray_interval(const float *vol, int64_t nx, int64_t ny, int64_t nz,
 }
 
 /* ------------------------------------------------------------------ */
+/* depth (section 2: what a catalogue overlay is tested against)      */
+/* ------------------------------------------------------------------ */
+/* Depth of one ray, as the ray parameter t = t0 + (k + 1/2) step of a
+ * sample k, or +inf:
+ *  composite: the first sample (among those taken, up to the stop) after
+ *             which the accumulated opacity A reaches `level`;
+ *  MIP:       the first sample whose value equals the ray's maximum.
+ * `count` samples are taken (the ray's n, or a flipped candidate), the stop
+ * test uses `tau`, the crossing test `level`. */
+static double depth_ray(const orc_scene *s, const orc_params *p, const ray_t *r, int64_t count, double tau,
+                        double level) {
+    int ert = tau < 1.0;
+    if (p->mode == 1) {
+        double m = -INFINITY, best = INFINITY;
+        for (int64_t k = 0; k < count; ++k) {
+            double pos[3], v;
+            sample_pos(r, p->step, k, pos);
+            if (p->filter == 1) {
+                double vl, vh;
+                int amb;
+                v = nearest(s, pos, p->eps_pos, &vl, &vh, &amb);
+            } else {
+                v = orc_trilinear(s, pos, NULL, NULL);
+            }
+            if (v > m) { m = v; best = r->t0 + (k + 0.5) * p->step; }
+        }
+        return best;
+    }
+    double A = 0.0;
+    for (int64_t k = 0; k < count; ++k) {
+        double pos[3], v, rgba[4];
+        sample_pos(r, p->step, k, pos);
+        if (p->filter == 1) {
+            double vl, vh;
+            int amb;
+            v = nearest(s, pos, p->eps_pos, &vl, &vh, &amb);
+        } else {
+            v = orc_trilinear(s, pos, NULL, NULL);
+        }
+        orc_lut(s->lut, s->nlut, s->vmin, s->vmax, v, rgba, NULL, NULL, NULL);
+        A += (1.0 - A) * rgba[3];
+        if (A >= level) return r->t0 + (k + 0.5) * p->step;
+        if (ert && A >= tau) break;
+    }
+    return INFINITY;
+}
+
+/* Per-pixel depth (see depth_ray).  lo / hi receive the smallest and largest
+ * depth over the flipped decisions: the sample count (n_lo, n, n_hi), the
+ * stop and crossing tests moved by -/+ eps_stop (composite), and, for MIP,
+ * every sample whose value could be the maximum once the values move by
+ * eps_val (trilinear: the FP32 interpolation's rounding) or the nearest
+ * cell flips.  flags gets FLAG_STOP when lo < hi for a composite, FLAG_CELL
+ * for a MIP tie, FLAG_COUNT as in orc_render. */
+int orc_depth(const float *vol, int64_t nx, int64_t ny, int64_t nz,
+              const float *lut, int32_t nlut, double vmin, double vmax,
+              const orc_camera *cam, const orc_params *p, double level, double eps_val,
+              const int32_t *pix, int64_t npix, double *out, double *lo, double *hi, int32_t *flags,
+              int nthreads) {
+    orc_scene s = {vol, nx, ny, nz, lut, nlut, vmin, vmax};
+    if (!pix) npix = (int64_t)cam->tile_w * cam->tile_h;
+    int nt = nthreads_of(nthreads);
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t x, y;
+        if (pix) { x = pix[2 * q]; y = pix[2 * q + 1]; }
+        else { x = q % cam->tile_w; y = q / cam->tile_w; }
+        ray_t r;
+        ray_prepare(&s, cam, p, cam->tile_x0 + x, cam->tile_y0 + y, &r);
+        double d = INFINITY, dl = INFINITY, dh = INFINITY;
+        int fl = 0;
+        if (r.hit) {
+            if (r.n_lo != r.n || r.n_hi != r.n) fl |= FLAG_COUNT;
+            d = depth_ray(&s, p, &r, r.n, p->tau, level);
+            dl = dh = d;
+            int64_t counts[3] = {r.n_lo, r.n, r.n_hi};
+            if (p->mode != 1) {
+                double taus[3] = {p->tau, p->tau - p->eps_stop, p->tau + p->eps_stop};
+                double levels[3] = {level, level - p->eps_stop, level + p->eps_stop};
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        for (int c = 0; c < 3; ++c) {
+                            double e = depth_ray(&s, p, &r, counts[a], taus[b], levels[c]);
+                            if (e < dl) dl = e;
+                            if (e > dh) dh = e;
+                        }
+                if (dl < dh) fl |= FLAG_STOP;
+            } else {
+                /* sample k can be the first maximum under some choice of
+                 * the values within their windows [vl, vh] iff its highest
+                 * value beats the lowest of every earlier sample strictly
+                 * and ties or beats the lowest of every later one (samples
+                 * past n_lo may be absent, so only those before n_lo must
+                 * be beaten) */
+                int64_t m = r.n_hi;
+                double *vl = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+                double *vh = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+                for (int64_t k = 0; k < m; ++k) {
+                    double pos[3], v;
+                    int amb = 0;
+                    sample_pos(&r, p->step, k, pos);
+                    if (p->filter == 1) v = nearest(&s, pos, p->eps_pos, &vl[k], &vh[k], &amb);
+                    else { v = orc_trilinear(&s, pos, NULL, NULL); vl[k] = v - eps_val; vh[k] = v + eps_val; }
+                    (void)v;
+                }
+                double pre = -INFINITY;
+                for (int64_t k = 0; k < m; ++k) {
+                    double suf = -INFINITY;
+                    for (int64_t j = k + 1; j < r.n_lo; ++j)
+                        if (vl[j] > suf) suf = vl[j];
+                    if (vh[k] > pre && vh[k] >= suf) {
+                        double t = r.t0 + (k + 0.5) * p->step;
+                        if (t < dl) dl = t;
+                        if (t > dh || dh == INFINITY) dh = t;
+                    }
+                    if (k < r.n_lo && vl[k] > pre) pre = vl[k];
+                }
+                free(vl);
+                free(vh);
+                if (d < dl) dl = d;
+                if (d != INFINITY && d > dh) dh = d;
+                if (dl < dh) fl |= FLAG_CELL;
+            }
+        }
+        out[q] = d;
+        if (lo) lo[q] = dl;
+        if (hi) hi[q] = dh;
+        if (flags) flags[q] = fl;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* catalogue overlay (section 2: source bounding cubes drawn as       */
+/* wireframe boxes over the render)                                   */
+/* ------------------------------------------------------------------ */
+/* Position of world point P in full-frame pixel coordinates (pixel (c, row)
+ * has its centre at (c + 1/2, row + 1/2)) and its view depth w (distance
+ * along f); perspective points need w > 0. */
+static void project_px(const orc_camera *c, const double f[3], const double r[3], const double u[3],
+                       const double P[3], double *X, double *Y, double *w) {
+    double d[3] = {P[0] - c->eye[0], P[1] - c->eye[1], P[2] - c->eye[2]};
+    double wf = d[0] * f[0] + d[1] * f[1] + d[2] * f[2];
+    double xr = d[0] * r[0] + d[1] * r[1] + d[2] * r[2];
+    double yu = d[0] * u[0] + d[1] * u[1] + d[2] * u[2];
+    double a, b, sx, sy;
+    if (c->kind == 1) {
+        double th = tan(c->fovy_deg * M_PI / 360.0);
+        a = th * c->full_w / c->full_h;
+        b = th;
+        sx = xr / wf;
+        sy = yu / wf;
+    } else {
+        a = c->half_w;
+        b = c->half_h;
+        sx = xr;
+        sy = yu;
+    }
+    *X = (sx / a + 1.0) * 0.5 * c->full_w;
+    *Y = (1.0 - sy / b) * 0.5 * c->full_h;
+    *w = wf;
+}
+
+/* Overlay n wireframe boxes (box i: lo[3], hi[3] in voxel coordinates, then
+ * straight RGBA; 10 doubles) on a premultiplied RGBA tile (image, modified
+ * in place).  For every pixel and every edge of every box: the edge (the
+ * part in front of the near plane w >= near for a perspective camera) is
+ * projected to full-frame pixel coordinates; the pixel is covered when the
+ * distance from its centre to the projected segment is at most half_width;
+ * the edge's depth there is the ray distance of the 3D point that projects
+ * to the segment's point nearest the centre (|P - eye| for a perspective
+ * camera, (P - eye).f for an orthographic one).  The edge is visible when
+ * that depth is at most depth[pixel] (depth NULL: always).  The pixel takes
+ * the nearest visible covering edge (ties: lower box, then lower edge
+ * index) and becomes rgba_premultiplied + (1 - a) image.  flags: 1 when a
+ * coverage, depth-test or nearest-edge decision lies within eps (relative
+ * to max(1, |quantity|)) of its threshold. */
+int orc_overlay(const orc_camera *cam, const double *boxes, int64_t n, double half_width, double near,
+                const float *depth, double eps, double *image, int32_t *flags, int nthreads) {
+    double f[3], r[3], u[3];
+    orc_basis(cam, f, r, u);
+    int64_t npix = (int64_t)cam->tile_w * cam->tile_h;
+    int nt = nthreads_of(nthreads);
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+    for (int64_t q = 0; q < npix; ++q) {
+        double qx = cam->tile_x0 + (double)(q % cam->tile_w) + 0.5;
+        double qy = cam->tile_y0 + (double)(q / cam->tile_w) + 0.5;
+        double zb = depth ? (double)depth[q] : INFINITY;
+        int64_t best_box = -1;
+        double best_t = INFINITY, second_t = INFINITY;   /* nearest two boxes */
+        int fl = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double *B = boxes + 10 * i;
+            double box_t = INFINITY;                      /* nearest visible edge of box i */
+            for (int e = 0; e < 12; ++e) {
+                /* edge e runs along axis e / 4; the other two axes take
+                 * lo or hi by the two bits of e % 4 */
+                int ax = e / 4, o1 = (ax + 1) % 3, o2 = (ax + 2) % 3;
+                double P0[3], P1[3];
+                P0[ax] = B[ax]; P1[ax] = B[3 + ax];
+                P0[o1] = P1[o1] = (e & 1) ? B[3 + o1] : B[o1];
+                P0[o2] = P1[o2] = (e & 2) ? B[3 + o2] : B[o2];
+                double X0, Y0, w0, X1, Y1, w1;
+                if (cam->kind == 1) {
+                    double wa = (P0[0] - cam->eye[0]) * f[0] + (P0[1] - cam->eye[1]) * f[1] +
+                                (P0[2] - cam->eye[2]) * f[2];
+                    double wb = (P1[0] - cam->eye[0]) * f[0] + (P1[1] - cam->eye[1]) * f[1] +
+                                (P1[2] - cam->eye[2]) * f[2];
+                    if (wa < near && wb < near) continue;
+                    if (wa < near || wb < near) {
+                        /* clip the part behind the near plane */
+                        double t = (near - wa) / (wb - wa);
+                        double C[3];
+                        for (int k = 0; k < 3; ++k) C[k] = P0[k] + t * (P1[k] - P0[k]);
+                        if (wa < near) memcpy(P0, C, sizeof C); else memcpy(P1, C, sizeof C);
+                    }
+                }
+                project_px(cam, f, r, u, P0, &X0, &Y0, &w0);
+                project_px(cam, f, r, u, P1, &X1, &Y1, &w1);
+                double dx = X1 - X0, dy = Y1 - Y0, L2 = dx * dx + dy * dy;
+                double sp = L2 > 0.0 ? ((qx - X0) * dx + (qy - Y0) * dy) / L2 : 0.0;
+                if (sp < 0.0) sp = 0.0;
+                if (sp > 1.0) sp = 1.0;
+                double ex = X0 + sp * dx - qx, ey = Y0 + sp * dy - qy;
+                double dist = sqrt(ex * ex + ey * ey);
+                if (fabs(dist - half_width) < eps * (half_width > 1.0 ? half_width : 1.0)) fl |= 1;
+                if (dist > half_width) continue;
+                double uu = cam->kind == 1 ? sp * w0 / (sp * w0 + (1.0 - sp) * w1) : sp;
+                double P[3], t;
+                for (int k = 0; k < 3; ++k) P[k] = P0[k] + uu * (P1[k] - P0[k]);
+                if (cam->kind == 1) {
+                    double d0 = P[0] - cam->eye[0], d1 = P[1] - cam->eye[1], d2 = P[2] - cam->eye[2];
+                    t = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                } else {
+                    t = (P[0] - cam->eye[0]) * f[0] + (P[1] - cam->eye[1]) * f[1] + (P[2] - cam->eye[2]) * f[2];
+                }
+                double sc = fabs(t) > 1.0 ? fabs(t) : 1.0;
+                if (isfinite(zb) && fabs(t - zb) < eps * sc) fl |= 1;
+                if (!(t <= zb)) continue;
+                if (t < box_t) box_t = t;
+            }
+            if (box_t < best_t) {
+                second_t = best_t;
+                best_t = box_t;
+                best_box = i;
+            } else if (box_t < second_t) {
+                second_t = box_t;
+            }
+        }
+        if (best_box >= 0 && second_t - best_t < eps * (fabs(best_t) > 1.0 ? fabs(best_t) : 1.0)) fl |= 1;
+        if (best_box >= 0) {
+            const double *c = boxes + 10 * best_box + 6;
+            double *px = image + 4 * q;
+            for (int k = 0; k < 3; ++k) px[k] = c[k] * c[3] + (1.0 - c[3]) * px[k];
+            px[3] = c[3] + (1.0 - c[3]) * px[3];
+        }
+        if (flags) flags[q] = fl;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* bricks                                                             */
 /* ------------------------------------------------------------------ */
 static int64_t brick_cell(double p, int64_t B, int64_t nb) {

@@ -197,16 +197,29 @@ MarchArgs vr_march_args(vr_ctx *ctx, const vr_render_params *p, const CamDev &ca
     return a;
 }
 
+// Depth in voxels below which no ray of a composite can stop early: with
+// every sample's opacity at most amax, A after n samples is at most
+// 1 - (1 - amax)^n, so A >= tau needs n >= log(1 - tau) / log(1 - amax).
+static double min_stop_depth(const vr_ctx *ctx, const vr_render_params *p) {
+    if (p->ert_alpha >= 1.0f || ctx->lut_amax <= 0.0f) return INFINITY;
+    if (ctx->lut_amax >= 1.0f || p->ert_alpha <= 0.0f) return 0.0;
+    const double n = std::log(1.0 - (double)p->ert_alpha) / std::log1p(-(double)ctx->lut_amax);
+    return std::ceil(n) * p->step;
+}
+
 // The LDS-staged kernel serves one-brick layouts; the direct-gather kernel
 // walks multi-brick layouts and serves as the fallback.  Automatic choice:
-// long rays (MIP, or composite without early termination) stage voxel boxes
-// in LDS; early-terminating composites, whose rays stop after a few samples,
-// gather directly.
+// long rays stage voxel boxes in LDS: MIP, composites without early
+// termination, and composites whose table is transparent enough that no ray
+// can stop within its first 64 voxels (min_stop_depth); other
+// early-terminating composites, whose rays may stop after a few samples,
+// gather directly.  Both kernels give bit-identical images, so the choice
+// only moves time.
 static bool use_slab_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single) return false;
     if (ctx->tune.path == 1 || ctx->tune.path == 3 || ctx->tune.waves_per_group < 4) return false;
     if (ctx->tune.path == 2) return true;
-    return p->mode == VR_MIP || p->ert_alpha >= 1.0f;
+    return p->mode == VR_MIP || p->ert_alpha >= 1.0f || min_stop_depth(ctx, p) >= 64.0;
 }
 
 // The compacting direct kernel (path 3) on one-brick layouts.
@@ -473,6 +486,21 @@ int vr_set_transfer_function(vr_ctx *ctx, const float *rgba_dev, int32_t n, floa
     ctx->lut.scale = (float)((double)(n - 1) / ((double)vmax - (double)vmin));
     ctx->vmax = vmax;
     ctx->has_lut = true;
+    // the table's largest opacity, read back once (4 KiB at most): it bounds
+    // how early a composite ray can stop, which picks the kernel (the images
+    // do not depend on it).  Unknown (1) on host-only contexts or a failed
+    // copy, which keeps the direct kernel for early-stopping composites.
+    ctx->lut_amax = 1.0f;
+    if (ctx->device >= 0) {
+        std::vector<float> h((size_t)n * 4);
+        if (hipMemcpy(h.data(), rgba_dev, h.size() * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess) {
+            float m = 0.0f;
+            for (int32_t i = 0; i < n; ++i) m = std::max(m, h[(size_t)i * 4 + 3]);
+            ctx->lut_amax = std::isfinite(m) ? std::min(m, 1.0f) : 1.0f;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     return ok(ctx);
 }
 

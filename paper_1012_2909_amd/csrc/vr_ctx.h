@@ -19,6 +19,7 @@ struct vr_ctx {
     bool has_lut = false;
     vr::LutDev lut{};
     float vmax = 1.0f;
+    float lut_amax = 1.0f;   // largest opacity of the table (kernel choice only)
     // camera
     bool has_camera = false;
     vr_camera cam{};
@@ -56,3 +57,4 @@ void *vr_stage(vr_ctx *ctx, size_t bytes);
 hipError_t vr_stage_copy(vr_ctx *ctx, void *dst, size_t bytes, hipStream_t s);
 
 int64_t vr_align256(int64_t x);
+

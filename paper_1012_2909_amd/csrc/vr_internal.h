@@ -125,4 +125,10 @@ hipError_t launch_batch_direct(const BatchArgs &a, int32_t mode, int32_t filter,
                                hipStream_t s);
 hipError_t launch_reset_u32(uint32_t *p, int32_t n, hipStream_t s);
 
+// K9: per-pixel depth of the render (one-brick layouts).
+hipError_t launch_depth(const MarchArgs &a, int32_t mode, int32_t filter, float level, float *depth, hipStream_t s);
+// K10: wireframe boxes over a premultiplied RGBA tile, depth-tested.
+hipError_t launch_overlay(const CamDev &cam, const vr_box *boxes, int32_t n, double hw, double near,
+                          const float *depth, float *img, hipStream_t s);
+
 }  // namespace vr

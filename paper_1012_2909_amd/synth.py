@@ -127,6 +127,28 @@ def add_source(cube, s, truncate):
     cube[z0:z1, y0:y1, x0:x1] = (sub.astype(np.float64) + blob).astype(np.float32)
 
 
+def catalogue_boxes(spec: CubeSpec, seed: int = 0, reach: float = 2.0, n_false: int = 0) -> np.ndarray:
+    """A source-finder-style catalogue of the cube: for every source, the
+    bounding cube of the voxels within `reach` sigma of its centre, as
+    (lo x, lo y, lo z, hi x, hi y, hi z) in voxel coordinates (voxel edges,
+    clipped to the cube), plus a straight RGBA colour drawn from
+    default_rng(seed); `n_false` extra boxes at random places stand for
+    spurious detections.  float32 (n, 10)."""
+    nz, ny, nx = spec.shape
+    rng = np.random.default_rng(seed)
+    rows = []
+    for cx, cy, cz, _amp, sx, sy, sz in draw_sources(spec):
+        lo = [max(0.0, math.floor(c - reach * sg)) for c, sg in ((cx, sx), (cy, sy), (cz, sz))]
+        hi = [min(float(n), math.ceil(c + reach * sg)) for c, sg, n in ((cx, sx, nx), (cy, sy, ny), (cz, sz, nz))]
+        rows.append(lo + hi + list(rng.uniform(0.2, 1.0, 3)) + [rng.uniform(0.5, 1.0)])
+    for _ in range(n_false):
+        c = [rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz)]
+        h = rng.uniform(1.0, 6.0, 3)
+        rows.append([c[0] - h[0], c[1] - h[1], c[2] - h[2], c[0] + h[0], c[1] + h[1], c[2] + h[2]] +
+                    list(rng.uniform(0.2, 1.0, 3)) + [rng.uniform(0.5, 1.0)])
+    return np.asarray(rows, dtype=np.float32).reshape(-1, 10)
+
+
 # --------------------------------------------------------------------------
 # transfer-function tables (straight RGBA, shape (n, 4), float32)
 # --------------------------------------------------------------------------

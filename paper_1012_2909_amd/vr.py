@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,6 +69,11 @@ SIGNATURES = [
     ("vr_set_camera", C.c_int, [P, C.POINTER(Camera)]),
     ("vr_render_workspace_bytes", I64, [P, C.POINTER(RenderParams)]),
     ("vr_render", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, P]),
+    ("vr_render_depth", C.c_int, [P, C.POINTER(RenderParams), C.c_float, P, P]),
+    ("vr_overlay_boxes", C.c_int, [P, P, I32, C.c_float, P, P, P]),
+    ("vr_pyramid_bytes", I64, [I32, I32, I32, P]),
+    ("vr_build_pyramid", C.c_int, [P, P, I32, I32, I32, P, I64, P]),
+    ("vr_write_pyramid_tiff", C.c_int, [C.c_char_p, P, I32, I32, I32, I32]),
     ("vr_count_samples", C.c_int, [P, C.POINTER(RenderParams), P, P]),
     ("vr_touched_bitmap_bytes", I64, [P]),
     ("vr_mark_touched_blocks", C.c_int, [P, C.POINTER(RenderParams), P, I64, P]),
@@ -150,6 +156,26 @@ def _stream():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def pyramid_levels(pyr, dims):
+    """Split a pyramid buffer (host or device uint8) into (h_l, w_l, 4) levels."""
+    out, off = [], 0
+    for h, w in dims:
+        out.append(pyr[off:off + h * w * 4].reshape(h, w, 4))
+        off += h * w * 4
+    return out
+
+
+def write_pyramid_tiff(path, pyramid, w, h, tile=256, bigtiff=False):
+    """Write a pyramid (uint8, host: numpy array or CPU tensor) as a pyramidal
+    tiled TIFF through the library's host writer."""
+    buf = pyramid.cpu().numpy() if torch.is_tensor(pyramid) else np.asarray(pyramid)
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    rc = lib().vr_write_pyramid_tiff(os.fsencode(path), buf.ctypes.data_as(C.c_void_p), int(w), int(h), int(tile),
+                                     1 if bigtiff else 0)
+    if rc != 0:
+        raise VRError(rc, lib().vr_last_error(None).decode())
 
 
 class Renderer:
@@ -274,6 +300,48 @@ class Renderer:
         if save:
             return out, workspace
         return out
+
+    def render_depth(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, trans="auto", level=0.5,
+                     out=None):
+        """Per-pixel depth (ray parameter t, +inf for none) of the render
+        with these settings: composite, where the opacity first reaches
+        `level`; MIP, the first maximum sample."""
+        p = params_struct(mode, filt, step, ert, trans, False)
+        w, h = self.cam.tile[2], self.cam.tile[3]
+        if out is None:
+            out = torch.empty((h, w), dtype=torch.float32, device=self.device)
+        self._check(lib().vr_render_depth(self.ctx, C.byref(p), float(level), _ptr(out), _stream()))
+        return out
+
+    def overlay_boxes(self, boxes, image, half_width=0.75, depth=None):
+        """Draw catalogue boxes ((n, 10) float32: lo xyz, hi xyz, straight
+        RGBA) as wireframes over `image` (the current view's (h, w, 4)
+        premultiplied tile, modified in place), hiding edges behind `depth`."""
+        if not torch.is_tensor(boxes):
+            boxes = torch.from_numpy(np.ascontiguousarray(boxes, dtype=np.float32))
+        b = boxes.to(self.device, torch.float32).contiguous()
+        assert b.ndim == 2 and b.shape[1] == 10
+        d = None if depth is None else depth.to(self.device, torch.float32).contiguous()
+        self._check(lib().vr_overlay_boxes(self.ctx, _ptr(b), int(b.shape[0]), float(half_width), _ptr(d),
+                                           _ptr(image), _stream()))
+        return image
+
+    def build_pyramid(self, image, tile=256):
+        """Display pyramid of a premultiplied RGBA (h, w, 4) float image:
+        (uint8 tensor of vr_pyramid_bytes, list of (h_l, w_l) per level)."""
+        img = image.to(self.device, torch.float32).contiguous()
+        h, w = int(img.shape[0]), int(img.shape[1])
+        levels = C.c_int32()
+        nbytes = int(lib().vr_pyramid_bytes(w, h, int(tile), C.byref(levels)))
+        if nbytes < 0:
+            raise VRError(nbytes, lib().vr_last_error(None).decode())
+        dst = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._check(lib().vr_build_pyramid(self.ctx, _ptr(img), w, h, int(tile), _ptr(dst), nbytes, _stream()))
+        dims = []
+        for _ in range(levels.value):
+            dims.append((h, w))
+            h, w = (h + 1) // 2, (w + 1) // 2
+        return dst, dims
 
     def render_backward(self, grad_out, workspace, grad_lut=None, grad_vol=None, step=0.5, ert=0.99,
                         trans="auto"):

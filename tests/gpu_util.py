@@ -7,23 +7,47 @@ import numpy as np
 #  - composite RGBA, FP32 storage: 1e-5 (the stated bar);
 #  - composite RGBA, FP16/BF16 storage against the oracle on the original
 #    FP32 cube: 2e-3; against the oracle on the storage-rounded cube: 1e-5;
-#  - trilinear MIP: the FP32 interpolation of 8 corners in 7 lerps, each a
-#    subtraction and an FMA, with weights converted from 32-bit fractions:
-#    one lerp level adds at most 5u M (u = 2^-24, M the largest corner
-#    magnitude: u|b-a| + u|r| + u f|b-a|), three levels 15u M, and the
-#    oracle's FP64 result is rounded once more (u |s|).  mip_tol(M) is that
-#    bound with M = the cube's largest magnitude; small test cubes use the
-#    looser-looking but there smaller 1e-6 |s| + 1e-6;
+#  - trilinear MIP: two parts.  (1) The FP32 interpolation of 8 corners in
+#    7 lerps, each a subtraction and an FMA, with weights converted from
+#    32-bit fractions: one lerp level adds at most 5u M (u = 2^-24, M the
+#    largest corner magnitude: u|b-a| + u|r| + u f|b-a|), three levels 15u M,
+#    and the oracle's FP64 result is rounded once more (u |s|): 16u M.
+#    (2) The sample positions: the GPU starts each ray at the fixed-point
+#    position rounded to 2^-32 and adds a per-sample increment rounded to
+#    2^-32 per axis, so sample k sits within (k + 1) 2^-33 voxel of the
+#    exact point on every axis; the trilinear field's slope along an axis is
+#    at most G, the largest difference of neighbouring voxels, so the value
+#    moves by at most 3 G (n + 1) 2^-33 over a ray of n samples.
+#    mip_tol(M) is part (1) alone, which small test cubes and short rays stay
+#    within; mip_tol(M, G, n) adds part (2) per pixel (n the ray's sample
+#    count) for the full-size cubes whose rays run to thousands of samples;
 #  - nearest MIP: bit-exact.
 TOL_COMPOSITE = 1e-5
 TOL_LOWP = 2e-3
 TOL_MIP_REL = 1e-6
 
 
-def mip_tol(vmax):
+def mip_tol(vmax, grad=None, n=None):
     """Absolute bound of |GPU - oracle| for a trilinear MIP value of a cube
-    whose largest magnitude is vmax (see above)."""
-    return 16.0 * 2.0 ** -24 * float(vmax)
+    whose largest magnitude is vmax; with grad (largest neighbour
+    difference) and n (samples of the pixel's ray, scalar or array) the
+    position term is added (see above)."""
+    t = 16.0 * 2.0 ** -24 * float(vmax)
+    if grad is not None and n is not None:
+        t = t + 3.0 * float(grad) * (np.asarray(n, dtype=np.float64) + 1.0) * 2.0 ** -33
+    return t
+
+
+def max_neighbour_diff(vol, planes=64):
+    """Largest |V[i+1] - V[i]| along any axis, in slabs of z-planes."""
+    g = 0.0
+    nz = vol.shape[0]
+    for z0 in range(0, nz, planes):
+        z1 = min(nz, z0 + planes + 1)
+        blk = np.asarray(vol[z0:z1], dtype=np.float32)
+        g = max(g, float(np.abs(np.diff(blk, axis=0)).max()) if blk.shape[0] > 1 else 0.0,
+                float(np.abs(np.diff(blk, axis=1)).max()), float(np.abs(np.diff(blk, axis=2)).max()))
+    return g
 
 
 def log(msg):

@@ -683,3 +683,124 @@ def test_bricked_candidates_bracket_the_result():
     clean = fl == 0
     assert np.array_equal(lo[clean], o[clean]) and np.array_equal(hi[clean], o[clean])
     assert ((fl & oracle.FLAG_STOP) != 0).any()
+
+
+# ----------------------------------------------------------------------------
+# depth and catalogue overlay
+# ----------------------------------------------------------------------------
+def test_depth_composite_closed_form():
+    """Constant alpha 1/2 along one axis ray (t0 = 1, step 1): A after k + 1
+    samples is 1 - 2^-(k+1), so the first crossing of level 0.8 is sample 2
+    (t = 3.5); level 0.5 is reached exactly at sample 0, a tie whose flipped
+    outcomes are samples 0 and 1 (t = 1.5, 2.5); a level above the early
+    stop's A is never reached."""
+    vol = np.full((8, 1, 1), 0.5, np.float32)
+    lut = synth.lut_dyadic([[0, 0, 0, 0], [1, 1, 1, 1]], 0.0, 1.0)
+    cam = _axis_ray_camera(0.5, 0.5)
+    d = oracle.depth(vol, lut, cam, step=1.0, tau=1.0, level=0.8)
+    assert d["out"][0, 0] == 3.5 and d["flags"][0, 0] == 0 and d["lo"][0, 0] == d["hi"][0, 0] == 3.5
+    d = oracle.depth(vol, lut, cam, step=1.0, tau=1.0, level=0.5, eps_stop=1e-3)
+    assert d["out"][0, 0] == 1.5 and d["lo"][0, 0] == 1.5 and d["hi"][0, 0] == 2.5
+    assert d["flags"][0, 0] & oracle.FLAG_STOP
+    # early stop at tau 0.7 (after sample 1, A = 3/4) comes before level 0.9
+    d = oracle.depth(vol, lut, cam, step=1.0, tau=0.7, level=0.9)
+    assert d["out"][0, 0] == np.inf
+
+
+def test_depth_mip_first_maximum():
+    """Nearest MIP along z through column x = 2 (t = z + 1): the maximum 9
+    sits in voxels z = 3 and z = 5; the depth is the first sample inside
+    z = 3 (z = 3.25 at step 0.5, t = 4.25).  A miss has infinite depth."""
+    vol = np.zeros((8, 1, 4), np.float32)
+    vol[3, 0, 2] = 9.0
+    vol[5, 0, 2] = 9.0
+    vol[6, 0, 1] = 11.0
+    lut = synth.lut_ramp()
+    d = oracle.depth(vol, lut, _axis_ray_camera(2.5, 0.5), mode="mip", filt="nearest")
+    assert d["out"][0, 0] == 4.25 and d["flags"][0, 0] == 0
+    d = oracle.depth(vol, lut, _axis_ray_camera(1.5, 0.5), mode="mip", filt="nearest")
+    assert d["out"][0, 0] == 7.25
+    d = oracle.depth(vol, lut, _axis_ray_camera(7.5, 0.5), mode="mip", filt="nearest")
+    assert d["out"][0, 0] == np.inf
+    # trilinear: samples at z = 3.25 and 3.75 both read 3/4 of the 9 (6.75),
+    # and so do z = 5.25 and 5.75; the first of them is the depth, and with a
+    # value window any of the four could be first
+    d = oracle.depth(vol, lut, _axis_ray_camera(2.5, 0.5), mode="mip")
+    assert d["out"][0, 0] == 4.25 and d["flags"][0, 0] == 0
+    d = oracle.depth(vol, lut, _axis_ray_camera(2.5, 0.5), mode="mip", eps_val=1e-6)
+    assert d["out"][0, 0] == 4.25
+    assert d["lo"][0, 0] == 4.25 and d["hi"][0, 0] == 6.75 and d["flags"][0, 0] & oracle.FLAG_CELL
+
+
+def test_overlay_orthographic_by_hand():
+    """View along +z over the 64^3 face at 256^2 (pixel centre (c+1/2,
+    row+1/2) <-> world (x, y) = ((c+1/2)/4, (row+1/2)/4)).  A box over
+    x in [8, 16], y in [8, 12], z in [10, 20]: its x-edges at y = 8 project
+    onto the pixel boundary Y = 32, so with half width 0.75 rows 31 and 32
+    are covered for columns 32..63, plus the corner caps at columns 31 and
+    64 (centre distance sqrt(1/2) < 0.75); row 30 and 33 are not (1.5).
+    Depth of the nearer edges is z + 1 = 11: a depth buffer of 15 keeps
+    them, one of 5 hides the box."""
+    cam = synth.camera_axis_z()
+    box = np.array([[8, 8, 10, 16, 12, 20, 1.0, 0.5, 0.25, 0.5]])
+    img0 = np.zeros((256, 256, 4))
+    img, fl = oracle.overlay(cam, box, img0, half_width=0.75)
+    col = np.array([0.5, 0.25, 0.125, 0.5])
+    assert (fl == 0).all()
+    for c in range(31, 65):
+        for r in (31, 32):
+            assert np.array_equal(img[r, c], col), (r, c)
+        assert not img[30, c].any()
+        # below the edge, rows 33.. belong to the y-edges at X = 32 and 64
+        # (columns 31, 32 and 63, 64) and nothing else
+        assert img[33, c].any() == (c in (31, 32, 63, 64)), c
+    assert not img[31, 30].any() and not img[31, 65].any()
+    # the y-edges at x = 16 (X = 64): columns 63 and 64 for rows 32..47
+    assert np.array_equal(img[40, 63], col) and np.array_equal(img[40, 64], col) and not img[40, 62].any()
+    # inside the box's outline nothing is drawn
+    assert not img[40, 40].any()
+    covered = img[..., 3] > 0
+    depth = np.full((256, 256), 15.0, np.float32)
+    img2, _ = oracle.overlay(cam, box, img0, half_width=0.75, depth=depth)
+    assert np.array_equal(img2, img)
+    img3, _ = oracle.overlay(cam, box, img0, half_width=0.75, depth=np.full((256, 256), 5.0, np.float32))
+    assert not img3.any()
+    # "over" an existing image: rgba a + (1 - a) under
+    under = np.full((256, 256, 4), 0.2)
+    img4, _ = oracle.overlay(cam, box, under, half_width=0.75)
+    assert np.allclose(img4[covered], col + 0.5 * 0.2, rtol=0, atol=1e-15)
+    assert np.array_equal(img4[~covered], under[~covered])
+
+
+def test_overlay_perspective_by_hand():
+    """Eye (0, 0, -10) looking along +z, fovy 90, 100 x 100: a point (x, y,
+    z) lands at X = (x/w + 1) 50, Y = (1 + y/w) 50 with w = z + 10.  The
+    segment (-5, 0, 0)..(5, 0, 0) maps to Y = 50, X in [25, 75]: rows 49
+    and 50 are covered for columns 25..74, and the depth there is the
+    distance sqrt(x^2 + 100) of the edge point under the pixel centre,
+    x = (X - 50)/5.  A second box straddling the eye's plane is clipped at
+    the near plane and does not disturb the first."""
+    cam = synth.Camera(synth.PERSPECTIVE, (0.0, 0.0, -10.0), (0.0, 0.0, 0.0), (0.0, -1.0, 0.0), fovy_deg=90.0,
+                       full_w=100, full_h=100)
+    # a flat box: its four x-edges coincide pairwise at y = 0, z = 0
+    box = np.array([[-5, 0, 0, 5, 0, 0, 0.0, 1.0, 0.0, 1.0]])
+    img, fl = oracle.overlay(cam, box, np.zeros((100, 100, 4)), half_width=0.75)
+    for c in range(25, 75):
+        assert img[49, c, 1] == 1.0 and img[50, c, 1] == 1.0 and img[48, c, 3] == 0 and img[51, c, 3] == 0
+    x = (np.arange(25, 75) + 0.5 - 50.0) / 5.0
+    expect = np.sqrt(x * x + 100.0)
+    # depth test right below / above the edge's distance at each column
+    dep = np.full((100, 100), np.inf, np.float32)
+    dep[49, 25:75] = (expect * (1 - 1e-6)).astype(np.float32)
+    dep[50, 25:75] = (expect * (1 + 1e-6)).astype(np.float32)
+    img2, _ = oracle.overlay(cam, box, np.zeros((100, 100, 4)), half_width=0.75, depth=dep)
+    assert not img2[49, 25:75].any() and (img2[50, 25:75, 1] == 1.0).all()
+    near_box = np.array([[-1, -1, -12, 1, 1, -8, 1.0, 0.0, 0.0, 1.0]])   # around the eye: clipped at the near plane
+    both = np.concatenate([box, near_box])
+    img3, _ = oracle.overlay(cam, both, np.zeros((100, 100, 4)), half_width=0.75)
+    assert np.isfinite(img3).all()
+    # every changed pixel took the nearer box's colour, and its clipped edges
+    # (which run off the frame from the near plane) do draw somewhere
+    changed = (img3 != img).any(axis=-1)
+    assert changed.any()
+    assert (img3[changed] == [1.0, 0.0, 0.0, 1.0]).all()
