@@ -229,6 +229,22 @@ int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *par
 int vr_render(vr_ctx *ctx, const vr_render_params *params, float *out_dev,
               void *workspace_dev, int64_t ws_bytes, void *stream);
 
+/* vr_render for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation).
+ * The only scratch a render needs without save_for_backward, the per-pixel
+ * ray records of MIP in object order (vr_render_workspace_bytes), lives in a
+ * fixed device array of vr_render_noalloc_max_bytes() = 128 MiB (ray records
+ * of up to 2^21 pixels), one per GPU, held until the process ends; the call
+ * allocates nothing.  The caller still passes the output.  Every call on one
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be ordered by the caller.  The
+ * records are fully rewritten by each call before they are read.
+ * Errors: EINVAL for save_for_backward (checkpoints must outlive the call:
+ * use vr_render with a workspace), ENOMEM when the render needs more
+ * scratch than the array holds, plus those of vr_render. */
+int64_t vr_render_noalloc_max_bytes(void);
+int vr_render_noalloc(vr_ctx *ctx, const vr_render_params *params, float *out_dev, void *stream);
+
 /* Samples each pixel's ray takes (up to and including the early stop),
  * int32 per pixel.  Used for throughput denominators; not a hot path. */
 int vr_count_samples(vr_ctx *ctx, const vr_render_params *params, int32_t *counts_dev, void *stream);

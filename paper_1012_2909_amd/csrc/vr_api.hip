@@ -354,6 +354,7 @@ int vr_create(vr_ctx **out, int device) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
+    vr_noalloc_setup(device);
     *out = c;
     return VR_OK;
 }

@@ -57,4 +57,7 @@ void *vr_stage(vr_ctx *ctx, size_t bytes);
 hipError_t vr_stage_copy(vr_ctx *ctx, void *dst, size_t bytes, hipStream_t s);
 
 int64_t vr_align256(int64_t x);
+// Resolve the device address of the fixed scratch array behind
+// vr_render_noalloc for `device` (which the caller has made current).
+void vr_noalloc_setup(int device);
 

@@ -69,6 +69,8 @@ SIGNATURES = [
     ("vr_set_camera", C.c_int, [P, C.POINTER(Camera)]),
     ("vr_render_workspace_bytes", I64, [P, C.POINTER(RenderParams)]),
     ("vr_render", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, P]),
+    ("vr_render_noalloc_max_bytes", I64, []),
+    ("vr_render_noalloc", C.c_int, [P, C.POINTER(RenderParams), P, P]),
     ("vr_render_depth", C.c_int, [P, C.POINTER(RenderParams), C.c_float, P, P]),
     ("vr_overlay_boxes", C.c_int, [P, P, I32, C.c_float, P, P, P]),
     ("vr_pyramid_bytes", I64, [I32, I32, I32, P]),
@@ -299,6 +301,17 @@ class Renderer:
                                     _ptr(workspace) if ws_bytes > 0 else None, ws_bytes, _stream()))
         if save:
             return out, workspace
+        return out
+
+    def render_noalloc(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, trans="auto", out=None):
+        """render() through vr_render_noalloc: the library's fixed scratch
+        instead of a workspace (no device allocation inside the call)."""
+        p = params_struct(mode, filt, step, ert, trans, False)
+        w, h = self.cam.tile[2], self.cam.tile[3]
+        shape = (h, w, 4) if mode == "composite" else (h, w)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        self._check(lib().vr_render_noalloc(self.ctx, C.byref(p), _ptr(out), _stream()))
         return out
 
     def render_depth(self, mode="composite", filt="trilinear", step=0.5, ert=0.99, trans="auto", level=0.5,
