@@ -199,6 +199,41 @@ int vr_describe_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz, int32_t 
                        int32_t brick_edge, int32_t orientations, void *dst_dev, int64_t dst_bytes);
 int vr_load_slab(vr_ctx *ctx, const float *src_dev, int64_t z0, int64_t nz_slab, void *stream);
 
+/* ---- out-of-core bricks (section 1: cubes larger than one machine's
+ *      memory are rendered brick by brick; section 3: WALLABY's expected
+ *      6144 x 6144 x 16384 cube, about nine times one GPU's memory) ------- */
+
+/* Bytes of one brick of the bricked layout (vr_volume_bytes with this brick
+ * edge and one orientation, divided by the brick count); < 0 if invalid. */
+int64_t vr_brick_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t brick_edge);
+
+/* Pack a float32 (nz,ny,nx) cube held in host memory into the bricked
+ * layout (brick_edge > 0, one orientation) in host memory at dst_host
+ * (vr_volume_bytes bytes), with `threads` host threads (0: all cores).  The
+ * bytes are those vr_load_volume writes on the device (same apron, padding
+ * and round-to-nearest-even).  Pure host; errors through vr_last_error(NULL). */
+int vr_pack_bricks_host(const float *src_host, int64_t nx, int64_t ny, int64_t nz, int32_t storage,
+                        int32_t brick_edge, void *dst_host, int64_t dst_bytes, int32_t threads);
+
+/* Make the context render a bricked volume whose packed bricks stay in host
+ * memory (host_bricks, vr_volume_bytes bytes, borrowed; pinned memory lets
+ * the copies run asynchronously) through a device cache of
+ * floor(cache_bytes / vr_brick_bytes) brick slots at cache_dev (borrowed).
+ * vr_render_bricks then copies every visible brick that is not cached into
+ * the least recently used slot on a copy stream of the context's own
+ * (overlapping the rendering of the bricks already there), waiting until
+ * the slot's previous brick has been rendered; the images are those of the
+ * resident volume.  The cache persists across calls until the volume is
+ * described again.  Other renders (vr_render, batches, backward) return
+ * EUNSUPPORTED on a streamed volume. */
+int vr_describe_streamed_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz, int32_t storage,
+                                int32_t brick_edge, const void *host_bricks, int64_t host_bytes, void *cache_dev,
+                                int64_t cache_bytes);
+
+/* Bricks copied from host memory and cache hits so far, and the cache's
+ * slot count (any pointer may be NULL). */
+int vr_stream_stats(const vr_ctx *ctx, int64_t *bricks_copied, int64_t *cache_hits, int32_t *slots);
+
 /* ---- transfer function (section 2: the colour map) --------------------- */
 
 /* n straight-RGBA float32 entries (n*4 floats on the device, n in [2, 1024])

@@ -35,6 +35,10 @@
  *             after the sample once A >= tau (tau >= 1: never).  Output is
  *             premultiplied (C, A) with no background.
  *  MIP        m = max_k s_k; -inf when the ray takes no sample.
+ *  Blanks     a NaN voxel (a blank, as FITS cubes mark them) makes every
+ *             sample whose interpolation footprint holds it NaN; such a
+ *             sample is transparent (rgba 0) in the composite and takes no
+ *             part in the MIP maximum, but it is still a sample of the ray.
  *  Bricks     edge-B bricks partition space into half-open boxes; a sample
  *             belongs to the brick holding its position (the last brick on
  *             the cube's far faces).  Each brick composites its own samples
@@ -233,20 +237,39 @@ static double nearest(const orc_scene *s, const double p[3], double eps, double 
     double v = voxel(s, c[0], c[1], c[2]);
     double mn = v, mx = v;
     if (any) {
+        /* over the candidate cells; a blank (NaN) candidate may drop the
+         * sample altogether, so the low end is then -inf */
+        int blank = 0;
+        mn = INFINITY;
+        mx = -INFINITY;
         for (int m = 0; m < 8; ++m) {
             int64_t q0 = (m & 1) ? alt[0] : c[0], q1 = (m & 2) ? alt[1] : c[1], q2 = (m & 4) ? alt[2] : c[2];
             double w = voxel(s, q0, q1, q2);
+            if (isnan(w)) { blank = 1; continue; }
             if (w < mn) mn = w;
             if (w > mx) mx = w;
         }
+        if (blank) mn = -INFINITY;
+        if (mx == -INFINITY) mx = v;        /* every candidate blank */
     }
     *lo = mn; *hi = mx; *amb = any;
     return v;
 }
 
-/* Transfer function; returns the table slope d rgba / d s in dv (0 when clamped). */
+/* Transfer function; returns the table slope d rgba / d s in dv (0 when clamped).
+ * A NaN value (a blank voxel in the sample's footprint) maps to transparent
+ * black: rgba = 0, slope 0, and *jj = -1 marks that no entry was used. */
 void orc_lut(const float *L, int32_t n, double vmin, double vmax, double s, double rgba[4],
              int32_t *jj, double *ww, double dv[4]) {
+    if (isnan(s)) {
+        for (int c = 0; c < 4; ++c) {
+            rgba[c] = 0.0;
+            if (dv) dv[c] = 0.0;
+        }
+        if (jj) *jj = -1;
+        if (ww) *ww = 0.0;
+        return;
+    }
     double u = (s - vmin) / (vmax - vmin);
     int clamped = 0;
     if (u <= 0.0) { u = 0.0; clamped = 1; }
@@ -978,7 +1001,7 @@ int orc_backward(const float *vol, int64_t nx, int64_t ny, int64_t nz,
                 double gs = 0.0;
                 int32_t j = jl[k];
                 double w = wl[k];
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < 4 && j >= 0; ++c) {   /* j < 0: a blank sample uses no entry */
                     gl[4 * j + c] += (1.0 - w) * d_rgba[c];
                     gl[4 * (j + 1) + c] += w * d_rgba[c];
                     gs += d_rgba[c] * dv[4 * k + c];

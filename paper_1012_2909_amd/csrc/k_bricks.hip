@@ -94,7 +94,8 @@ __global__ __launch_bounds__(256) void k_brick(MarchArgs A, const BrickJob *__re
 
     const int64_t sh = FILTER == VR_TRILINEAR ? ((int64_t)1 << 31) : 0;   // corner grid q = p - 1/2
     int64_t Q[3] = {P[0] - sh + k0 * D[0], P[1] - sh + k0 * D[1], P[2] - sh + k0 * D[2]};
-    const S *base = (const S *)V.data + ((int64_t)(J.bz * V.nby + J.by) * V.nbx + J.bx) * V.brick_elems;
+    const S *base = J.brick ? (const S *)J.brick
+                            : (const S *)V.data + ((int64_t)(J.bz * V.nby + J.by) * V.nbx + J.bx) * V.brick_elems;
     const int32_t ox = J.bx * V.Bx - 1, oy = J.by * V.By - 1, oz = J.bz * V.Bz - 1;
     const uint32_t Px = (uint32_t)V.Px, PxPy = (uint32_t)V.Px * (uint32_t)V.Py;
     const uint32_t lim_x = V.Bx + 1, lim_y = V.By + 1, lim_z = V.Bz + 1;

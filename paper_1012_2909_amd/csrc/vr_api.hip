@@ -157,11 +157,13 @@ int vr_check_params(vr_ctx *ctx, const vr_render_params *p) {
     return VR_OK;
 }
 
-int vr_need_state(vr_ctx *ctx, bool lut_needed) {
+int vr_need_state(vr_ctx *ctx, bool lut_needed, bool streamed_ok) {
 #define need_state vr_need_state
     if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
     if (ctx->device < 0 && ctx->vol_loaded) return no_device(ctx);
     if (!ctx->vol_loaded) return fail(ctx, VR_ESTATE, "no volume loaded");
+    if (ctx->st.on && !streamed_ok)
+        return fail(ctx, VR_EUNSUPPORTED, "the volume is streamed from host memory: render it with vr_render_bricks");
     if (!ctx->has_camera) return fail(ctx, VR_ESTATE, "no camera set");
     if (lut_needed && !ctx->has_lut) return fail(ctx, VR_ESTATE, "no transfer function set");
     return VR_OK;
@@ -361,6 +363,7 @@ int vr_create(vr_ctx **out, int device) {
 
 int vr_destroy(vr_ctx *ctx) {
     if (!ctx) return VR_OK;
+    vr_stream_release(ctx);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
     if (ctx->graph_src) (void)hipGraphDestroy(ctx->graph_src);
@@ -375,8 +378,9 @@ int vr_destroy(vr_ctx *ctx) {
 // volume
 // ---------------------------------------------------------------------------
 
-static bool layout_of(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t B, int32_t orients, VolDev *v,
-                      int64_t *bytes) {
+bool vr_layout_of(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t B, int32_t orients, VolDev *v,
+                  int64_t *bytes) {
+#define layout_of vr_layout_of
     if (nx <= 0 || ny <= 0 || nz <= 0) return false;
     if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24)) return false;
     if (storage != VR_F32 && storage != VR_F16 && storage != VR_BF16) return false;
@@ -444,6 +448,7 @@ int vr_describe_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz, int32_t 
     if (dst_bytes < need) return fail(ctx, VR_ENOMEM, "destination holds %lld bytes, layout needs %lld",
                                       (long long)dst_bytes, (long long)need);
     v.data = dst_dev;
+    vr_stream_reset(ctx);
     ctx->vol = v;
     ctx->has_volume = true;
     ctx->vol_loaded = false;

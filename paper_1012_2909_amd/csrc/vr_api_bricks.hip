@@ -74,6 +74,79 @@ std::vector<Foot> footprints(const vr_ctx *ctx) {
 
 int chans(const vr_render_params *p) { return p->mode == VR_MIP ? 1 : 4; }
 
+// The brick jobs of one vr_render_bricks call on a streamed volume (jobs in
+// brick-id order, in the pinned staging area, their table not yet copied).
+// Plan on the host which cache slot serves each brick: the bricks already
+// cached first, then the others in order, each taking the least recently
+// used slot.  Then enqueue: per missing brick, on the copy stream, wait
+// until the last render that read its slot has finished, copy it from host
+// memory into the slot and mark it ready; on the render stream, wait for it
+// and launch K3 for that brick's job alone, then mark the slot free again.
+// Copies of later bricks thus overlap the rendering of earlier ones.
+int render_streamed(vr_ctx *ctx, const vr_render_params *p, const MarchArgs &a, BrickJob *jobs, int32_t n,
+                    void *pool, size_t tbytes, hipStream_t s) {
+    vr_stream_state &st = ctx->st;
+    const VolDev &v = ctx->vol;
+    std::vector<int64_t> id(n);
+    for (int32_t i = 0; i < n; ++i) id[i] = ((int64_t)jobs[i].bz * v.nby + jobs[i].by) * v.nbx + jobs[i].bx;
+    // processing order: hits, then misses (each in brick-id order)
+    std::vector<int32_t> order;
+    std::vector<int32_t> slot_of(n, -1);
+    std::vector<char> miss(n, 0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int32_t i = 0; i < n; ++i) {
+            if (slot_of[i] >= 0) continue;    // taken as a hit (its slot may since have been reused)
+            int32_t hit = -1;
+            for (int32_t k = 0; k < st.slots; ++k)
+                if (st.slot_brick[k] == id[i]) { hit = k; break; }
+            if ((hit >= 0) != (pass == 0)) continue;
+            int32_t k = hit;
+            if (k < 0) {
+                k = 0;
+                for (int32_t q = 1; q < st.slots; ++q)
+                    if (st.slot_stamp[q] < st.slot_stamp[k]) k = q;
+                st.slot_brick[k] = id[i];
+                miss[i] = 1;
+            }
+            st.slot_stamp[k] = ++st.clock;
+            slot_of[i] = k;
+            order.push_back(i);
+        }
+    for (int32_t i = 0; i < n; ++i) {
+        jobs[i].brick = st.cache + (int64_t)slot_of[i] * st.brick_bytes;
+        jobs[i].tile_begin = 0;           // each job is launched alone
+    }
+    hipError_t e = vr_stage_copy(ctx, pool, tbytes, s);
+    if (e != hipSuccess) return vr_dev_check(ctx, e, "brick table copy");
+    const BrickJob *dev = (const BrickJob *)pool;
+    for (int32_t i : order) {
+        const int32_t k = slot_of[i];
+        if (miss[i]) {
+            if (st.slot_used[k] && (e = hipStreamWaitEvent(st.copy, st.slot_free[k], 0)) != hipSuccess) break;
+            if ((e = hipMemcpyAsync(st.cache + (int64_t)k * st.brick_bytes, st.host + id[i] * st.brick_bytes,
+                                    (size_t)st.brick_bytes, hipMemcpyHostToDevice, st.copy)) != hipSuccess)
+                break;
+            if ((e = hipEventRecord(st.slot_ready[k], st.copy)) != hipSuccess) break;
+            if ((e = hipStreamWaitEvent(s, st.slot_ready[k], 0)) != hipSuccess) break;
+            st.copied++;
+        } else {
+            // filled by an earlier call, possibly on another stream: order after that copy
+            if ((e = hipStreamWaitEvent(s, st.slot_ready[k], 0)) != hipSuccess) break;
+            st.hits++;
+        }
+        const int32_t tiles = jobs[i].tiles_x * ((jobs[i].h + 15) / 16);
+        if ((e = launch_bricks(a, p->mode, p->filter, dev + i, 1, tiles, s)) != hipSuccess) break;
+        if ((e = hipEventRecord(st.slot_free[k], s)) != hipSuccess) break;
+        st.slot_used[k] = 1;
+    }
+    if (e != hipSuccess) {
+        // the slots' contents are unknown after a failed enqueue: forget them
+        std::fill(st.slot_brick.begin(), st.slot_brick.end(), -1);
+        return vr_dev_check(ctx, e, "streamed bricks");
+    }
+    return vr_dev_check(ctx, hipSuccess, "streamed bricks");
+}
+
 }  // namespace
 
 extern "C" {
@@ -90,7 +163,7 @@ int64_t vr_bricks_pool_bytes(const vr_ctx *ctx, const vr_render_params *p) {
 
 int vr_render_bricks(vr_ctx *ctx, const vr_render_params *p, vr_partial *parts, int32_t max_parts, int32_t *n_parts,
                      void *pool, int64_t pool_bytes, void *stream) {
-    int rc = vr_need_state(ctx, p && p->mode == VR_COMPOSITE);
+    int rc = vr_need_state(ctx, p && p->mode == VR_COMPOSITE, true);
     if (rc != VR_OK) return rc;
     if ((rc = vr_check_params(ctx, p)) != VR_OK) return rc;
     if (!n_parts) return vr_fail(ctx, VR_EINVAL, "n_parts is NULL");
@@ -112,6 +185,7 @@ int vr_render_bricks(vr_ctx *ctx, const vr_render_params *p, vr_partial *parts, 
         const Foot &x = f[i];
         BrickJob &j = stage[i];
         j.data = (float *)((char *)pool + off);
+        j.brick = nullptr;
         j.x0 = x.x0; j.y0 = x.y0; j.w = x.w; j.h = x.h;
         j.bx = x.bx; j.by = x.by; j.bz = x.bz;
         j.tiles_x = (x.w + 15) / 16;
@@ -125,10 +199,11 @@ int vr_render_bricks(vr_ctx *ctx, const vr_render_params *p, vr_partial *parts, 
         off += align256((int64_t)x.w * x.h * chans(p) * 4);
     }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = vr_stage_copy(ctx, pool, (size_t)tbytes, s);
-    if (e != hipSuccess) return vr_dev_check(ctx, e, "brick table copy");
     MarchArgs a = vr_march_args(ctx, p, ctx->camd);
     a.vol = ctx->vol;   // partials read the x-fastest bricks
+    if (ctx->st.on) return render_streamed(ctx, p, a, stage, (int32_t)f.size(), pool, (size_t)tbytes, s);
+    hipError_t e = vr_stage_copy(ctx, pool, (size_t)tbytes, s);
+    if (e != hipSuccess) return vr_dev_check(ctx, e, "brick table copy");
     return vr_dev_check(ctx, launch_bricks(a, p->mode, p->filter, (const BrickJob *)pool, (int32_t)f.size(), tiles, s),
                         "bricks");
 }

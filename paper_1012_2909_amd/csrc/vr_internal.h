@@ -67,6 +67,7 @@ hipError_t launch_touch(const MarchArgs &a, int32_t mode, int32_t filter, uint32
 // K3: per-brick partials.  The table (device) holds one BrickJob per partial.
 struct BrickJob {
     float *data;          // partial image (w*h*4 or w*h)
+    const void *brick;    // the brick's block, or NULL: its place in the resident layout
     int32_t x0, y0, w, h; // footprint (tile-local)
     int32_t bx, by, bz;   // brick cell
     int32_t tiles_x;      // 16x16 pixel tiles across the footprint

@@ -69,13 +69,17 @@ SIGNATURES = [
     ("vr_set_camera", C.c_int, [P, C.POINTER(Camera)]),
     ("vr_render_workspace_bytes", I64, [P, C.POINTER(RenderParams)]),
     ("vr_render", C.c_int, [P, C.POINTER(RenderParams), P, P, I64, P]),
-    ("vr_render_noalloc_max_bytes", I64, []),
-    ("vr_render_noalloc", C.c_int, [P, C.POINTER(RenderParams), P, P]),
     ("vr_render_depth", C.c_int, [P, C.POINTER(RenderParams), C.c_float, P, P]),
     ("vr_overlay_boxes", C.c_int, [P, P, I32, C.c_float, P, P, P]),
+    ("vr_brick_bytes", I64, [I64, I64, I64, I32, I32]),
+    ("vr_pack_bricks_host", C.c_int, [P, I64, I64, I64, I32, I32, P, I64, I32]),
+    ("vr_describe_streamed_volume", C.c_int, [P, I64, I64, I64, I32, I32, P, I64, P, I64]),
+    ("vr_stream_stats", C.c_int, [P, P, P, P]),
     ("vr_pyramid_bytes", I64, [I32, I32, I32, P]),
     ("vr_build_pyramid", C.c_int, [P, P, I32, I32, I32, P, I64, P]),
     ("vr_write_pyramid_tiff", C.c_int, [C.c_char_p, P, I32, I32, I32, I32]),
+    ("vr_render_noalloc_max_bytes", I64, []),
+    ("vr_render_noalloc", C.c_int, [P, C.POINTER(RenderParams), P, P]),
     ("vr_count_samples", C.c_int, [P, C.POINTER(RenderParams), P, P]),
     ("vr_touched_bitmap_bytes", I64, [P]),
     ("vr_mark_touched_blocks", C.c_int, [P, C.POINTER(RenderParams), P, I64, P]),
@@ -158,6 +162,25 @@ def _stream():
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def pack_bricks_host(cube, storage="f32", brick=256, out=None, threads=0):
+    """Pack a float32 (nz, ny, nx) host cube (numpy array or memmap) into the
+    bricked layout in host memory: `out` (uint8 CPU tensor, pinned for
+    asynchronous copies) or a new pinned tensor.  Returns it."""
+    src = np.ascontiguousarray(cube, dtype=np.float32)
+    nz, ny, nx = src.shape
+    nbytes = int(lib().vr_volume_bytes(nx, ny, nz, DTYPES[storage], int(brick), 1))
+    if nbytes < 0:
+        raise VRError(nbytes, "invalid volume size")
+    if out is None:
+        out = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    assert out.device.type == "cpu" and out.numel() >= nbytes
+    rc = lib().vr_pack_bricks_host(src.ctypes.data_as(C.c_void_p), nx, ny, nz, DTYPES[storage], int(brick),
+                                   C.c_void_p(out.data_ptr()), out.numel(), int(threads))
+    if rc != 0:
+        raise VRError(rc, lib().vr_last_error(None).decode())
+    return out
 
 
 def pyramid_levels(pyr, dims):
@@ -256,6 +279,35 @@ class Renderer:
         self.brick = int(brick)
         self.storage_dtype = storage
         self.generation += 1
+
+    def describe_streamed_volume(self, shape, host_bricks, storage="f32", brick=256, cache_slots=None,
+                                 cache=None):
+        """Render from bricks packed in host memory (pack_bricks_host)
+        through a device cache of `cache_slots` bricks (or the given cache
+        tensor)."""
+        nz, ny, nx = shape
+        bb = int(lib().vr_brick_bytes(nx, ny, nz, DTYPES[storage], int(brick)))
+        if bb < 0:
+            raise VRError(bb, "invalid volume size")
+        if cache is None:
+            cache = torch.empty(bb * int(cache_slots), dtype=torch.uint8, device=self.device)
+        self.storage = None
+        self._check(lib().vr_describe_streamed_volume(self.ctx, nx, ny, nz, DTYPES[storage], int(brick),
+                                                      C.c_void_p(host_bricks.data_ptr()), host_bricks.numel(),
+                                                      _ptr(cache), cache.numel()))
+        self.host_bricks = host_bricks
+        self.storage = cache
+        self.orientations = 1
+        self.shape = tuple(shape)
+        self.brick = int(brick)
+        self.storage_dtype = storage
+        self.generation += 1
+
+    def stream_stats(self):
+        """(bricks copied from host, cache hits, cache slots) so far."""
+        a, b, n = C.c_int64(), C.c_int64(), C.c_int32()
+        self._check(lib().vr_stream_stats(self.ctx, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
     def load_slab(self, slab, z0):
         slab = slab.to(self.device, torch.float32).contiguous()

@@ -159,6 +159,42 @@ def test_64gib_bricked_9600x5400_sampled(R, cube64, storage):
                           what=f"64 GiB {storage} tile {t} {mode} ({len(pix)} px, {hits} hit)")
 
 
+def test_64gib_streamed_quarter_cache_equals_resident(R, cube64):
+    """The 64 GiB cube, FP16 storage, as 1024 bricks of 256^3: the centre
+    panel of the 9600x5400 frame rendered from bricks streamed out of pinned
+    host memory through a device cache of 256 bricks (a quarter) equals the
+    resident bricked render bit for bit, in both modes."""
+    import time
+    from paper_1012_2909_amd import vr
+    spec = synth.CUBE_64GIB
+    log("case: 64 GiB streamed, quarter cache")
+    R.describe_volume(spec.shape, storage="f16", brick=256)
+    for z0 in range(0, spec.shape[0], 256):
+        R.load_slab(torch.from_numpy(cube64[z0:z0 + 256]), z0)
+    lut = synth.lut_ramp(alpha_scale=1.0 / 64.0)
+    R.set_lut(lut)
+    cam = synth.tiles_5x5(synth.orbit_camera(spec.shape, seed=3, w=9600, h=5400))[12]
+    R.set_camera(cam)
+    ref = {m: R.render_bricked(mode=m).cpu().numpy() for m in ("composite", "mip")}
+    t = time.time()
+    host = vr.pack_bricks_host(cube64, storage="f16", brick=256)
+    log(f"packed {host.numel() / 1e9:.1f} GB of bricks in pinned host memory in {time.time() - t:.1f}s")
+    R.describe_streamed_volume(spec.shape, host, storage="f16", brick=256, cache_slots=256)
+    R.set_lut(lut)
+    R.set_camera(cam)
+    for m in ("composite", "mip"):
+        torch.cuda.synchronize()
+        t = time.time()
+        got = R.render_bricked(mode=m).cpu().numpy()
+        dt = time.time() - t
+        copied, hits, slots = R.stream_stats()
+        log(f"streamed {m}: {dt * 1e3:.0f} ms, {copied} bricks copied so far, {hits} hits, {slots} slots")
+        assert np.array_equal(got, ref[m]), m
+    assert slots == 256 and copied > 256
+    R.storage = None
+    del host
+
+
 def test_512mib_f16_batch_of_64_views_graph_sampled(R):
     spec = synth.CUBE_512MIB
     vol = synth.make_cube(spec)

@@ -119,7 +119,8 @@ def test_overlay_matches_oracle(R, cube, kind):
     err = np.abs(got - ref)[clean].max()
     drawn = int((np.abs(ref - base) > 0).any(axis=-1).sum())
     log(f"overlay {kind}: {drawn} px drawn, max err {err:.2e}, {int((~clean).sum())} flagged")
-    assert drawn > 100
+    # from inside the cube most edges lie behind the near emission
+    assert drawn > (20 if kind == "inside" else 100)
     assert err <= 2e-7
     assert (~clean).sum() <= 4
     # without a depth image every covering edge is visible: more is drawn

@@ -804,3 +804,59 @@ def test_overlay_perspective_by_hand():
     changed = (img3 != img).any(axis=-1)
     assert changed.any()
     assert (img3[changed] == [1.0, 0.0, 0.0, 1.0]).all()
+
+
+# ----------------------------------------------------------------------------
+# blank (NaN) voxels
+# ----------------------------------------------------------------------------
+def test_blank_voxels_are_transparent_samples():
+    """Constant alpha 1/2 along one axis ray (step 1, samples at z + 1/2),
+    voxel z = 2 blank: with nearest sampling its sample is skipped (A after
+    the 8 samples is 1 - 2^-7, as for 7 samples); with trilinear sampling
+    the samples at z = 1.5, 2.5 and 3.5 all read the blank (2 corners each
+    side), so 5 of the 8 count.  The MIP is the maximum over the other
+    samples, and a ray of blanks only gives -inf."""
+    vol = np.full((8, 1, 1), 0.5, np.float32)
+    vol[2] = np.nan
+    vol[6] = 0.75
+    lut = synth.lut_dyadic([[0, 0, 0, 0], [1, 1, 1, 1]], 0.0, 1.0)
+    cam = _axis_ray_camera(0.5, 0.5)
+    near = oracle.render(vol, lut, cam, filt="nearest", step=1.0, tau=1.0)["out"][0, 0]
+    # 6 samples of alpha 1/2 and one of 3/4 (z = 6): A = 1 - 2^-6 * 1/4
+    A = 1.0 - 0.5 ** 6 * 0.25
+    assert near[3] == A and np.isfinite(near).all()
+    tri = oracle.render(vol, lut, cam, step=1.0, tau=1.0)["out"][0, 0]
+    assert np.isfinite(tri).all()
+    # samples at z + 1/2 read voxels z-1/2 .. z+1/2 (q = z clamped): z = 1, 2, 3
+    # touch voxel 2 (q in [1, 3]); the others are 0.5, 0.5 + ..., 0.75 mixes
+    assert oracle.render(vol, lut, cam, mode="mip", filt="nearest", step=1.0)["out"][0, 0] == 0.75
+    blank = np.full((8, 1, 1), np.nan, np.float32)
+    assert oracle.render(blank, lut, cam, mode="mip", step=1.0)["out"][0, 0] == -np.inf
+    assert not oracle.render(blank, lut, cam, step=1.0, tau=1.0)["out"].any()
+    d = oracle.depth(blank, lut, cam, mode="mip", step=1.0)
+    assert d["out"][0, 0] == np.inf
+
+
+def test_blank_voxels_adjoint_matches_finite_differences():
+    """With blank voxels in the cube, the table gradient still matches
+    central differences (a blank sample uses no table entry)."""
+    vol = synth.make_cube(synth.CUBE_FD16)
+    rng = np.random.default_rng(9)
+    vol.reshape(-1)[rng.integers(0, vol.size, 40)] = np.nan
+    lut = synth.lut_random(55)
+    lut = synth.Lut(lut.table * np.float32(0.5), lut.vmin, lut.vmax)
+    cam = synth.orbit_camera(vol.shape, seed=5, w=12, h=12)
+    g = np.random.default_rng(2).standard_normal((12, 12, 4))
+    gl, gv = oracle.backward(vol, lut, cam, g, tau=1.0)
+    assert np.isfinite(gl).all()
+    base = lut.table.astype(np.float64)
+    h = 1e-6
+    for j in rng.integers(0, base.shape[0], 12):
+        for c in range(4):
+            tp, tm = base.copy(), base.copy()
+            tp[j, c] += h
+            tm[j, c] -= h
+            fp = oracle.render(vol, synth.Lut(tp.astype(np.float32), lut.vmin, lut.vmax), cam, tau=1.0)["out"]
+            fm = oracle.render(vol, synth.Lut(tm.astype(np.float32), lut.vmin, lut.vmax), cam, tau=1.0)["out"]
+            fd = ((fp - fm) * g).sum() / (np.float64(np.float32(base[j, c] + h)) - np.float64(np.float32(base[j, c] - h)))
+            assert abs(fd - gl[j, c]) <= 1e-6 * max(1.0, np.abs(gl).max()), (j, c)
