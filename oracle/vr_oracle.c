@@ -25,8 +25,12 @@
  *             t1 = tf; a ray misses when t1 <= t0.  A zero direction
  *             component keeps the ray iff the origin lies in that slab.
  *  Samples    t_k = t0 + (k + 1/2) step for k = 0, 1, ... while t_k < t1.
- *  Trilinear  q = p - 1/2 per axis, clamped to [0, N-1]; i = min(floor q, N-2);
- *             f = q - i; interpolate along x, then y, then z (N = 1: i=0, f=0).
+ *  Trilinear  q = p - 1/2 per axis; corners floor(q) and floor(q) + 1, each
+ *             clamped to [0, N-1] (the cube extended by repeating its
+ *             faces), weight f = q - floor(q) on the second; interpolate
+ *             along x, then y, then z.  Inside the cube this is plain
+ *             trilinear interpolation, and beyond its outer voxel centres
+ *             the value is the edge voxel's (clamp-to-edge).
  *  Nearest    i = clamp(floor p, 0, N-1).
  *  Table      u = clamp((s - vmin)/(vmax - vmin), 0, 1); x = u (n-1);
  *             j = min(floor x, n-2); w = x - j; rgba = (1-w) L[j] + w L[j+1];
@@ -172,25 +176,29 @@ static double voxel(const orc_scene *s, int64_t i, int64_t j, int64_t k) {
     return (double)s->vol[(k * s->ny + j) * s->nx + i];
 }
 
-static void tri_axis(double p, int64_t n, int64_t *i, double *f) {
-    if (n == 1) { *i = 0; *f = 0.0; return; }
+/* Clamp-to-edge, read as the cube extended by repeating its faces: the two
+ * corners of axis position p are the voxels floor(q) and floor(q) + 1 of
+ * q = p - 1/2, each index clamped to [0, n-1], with weight f = q - floor(q)
+ * on the second.  Inside [0, n-1] this is plain linear interpolation; beyond
+ * it both corners are the edge voxel, so the value is the edge voxel's.  The
+ * two corners are the sample's footprint along the axis (what makes it blank
+ * when one holds a NaN). */
+static void tri_axis(double p, int64_t n, int64_t *i0, int64_t *i1, double *f) {
     double q = p - 0.5;
-    if (q < 0.0) q = 0.0;
-    if (q > (double)(n - 1)) q = (double)(n - 1);
-    int64_t fi = (int64_t)floor(q);
-    if (fi > n - 2) fi = n - 2;
-    *i = fi;
-    *f = q - (double)fi;
+    double fl = floor(q);
+    int64_t a = (int64_t)fl, b = a + 1;
+    *i0 = a < 0 ? 0 : (a > n - 1 ? n - 1 : a);
+    *i1 = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
+    *f = q - fl;
 }
 
 /* Trilinear value; corners/weights returned for the adjoint when wanted. */
 double orc_trilinear(const orc_scene *s, const double p[3], int64_t idx[8], double wt[8]) {
-    int64_t i, j, k;
+    int64_t i, j, k, i1, j1, k1;
     double fx, fy, fz;
-    tri_axis(p[0], s->nx, &i, &fx);
-    tri_axis(p[1], s->ny, &j, &fy);
-    tri_axis(p[2], s->nz, &k, &fz);
-    int64_t i1 = s->nx > 1 ? i + 1 : i, j1 = s->ny > 1 ? j + 1 : j, k1 = s->nz > 1 ? k + 1 : k;
+    tri_axis(p[0], s->nx, &i, &i1, &fx);
+    tri_axis(p[1], s->ny, &j, &j1, &fy);
+    tri_axis(p[2], s->nz, &k, &k1, &fz);
     double c000 = voxel(s, i, j, k), c100 = voxel(s, i1, j, k);
     double c010 = voxel(s, i, j1, k), c110 = voxel(s, i1, j1, k);
     double c001 = voxel(s, i, j, k1), c101 = voxel(s, i1, j, k1);

@@ -110,14 +110,15 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
                 const int j = min((int)x, n_l - 2);
                 const float w = x - (float)j;
                 const float4 La = lut[j], Lb = lut[j + 1];
+                const bool blank = !(s == s);              // NaN: transparent, uses no table entry
                 const float c0 = fmaf(w, Lb.x - La.x, La.x), c1 = fmaf(w, Lb.y - La.y, La.y);
-                const float c2 = fmaf(w, Lb.z - La.z, La.z), a = fmaf(w, Lb.w - La.w, La.w);
+                const float c2 = fmaf(w, Lb.z - La.z, La.z), a = blank ? 0.0f : fmaf(w, Lb.w - La.w, La.w);
                 const float Tk = tbuf[(k - k0) * blockDim.x + tid];
                 const float ta = Tk * a;
                 const float d0 = g.x * ta, d1 = g.y * ta, d2 = g.z * ta;
                 const float da = Tk * (g.x * (c0 - S0) + g.y * (c1 - S1) + g.z * (c2 - S2) + g.w * P);
                 // table gradient (LDS-privatised)
-                if (B.grad_lut) {
+                if (B.grad_lut && !blank) {
                     const float wa = 1.0f - w;
                     atomicAdd(&glut[4 * j + 0], wa * d0);
                     atomicAdd(&glut[4 * j + 1], wa * d1);

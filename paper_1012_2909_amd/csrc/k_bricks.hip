@@ -17,33 +17,6 @@
 
 namespace vr {
 
-// Samples k in [0, n) with lo <= P(k) < hi along one axis, P(k) = P0 + k S
-// (fixed point); returns [k0, k1).  hi_closed admits P(k) == hi.
-__device__ __forceinline__ void axis_range(int64_t P0, int64_t S, int64_t lo, int64_t hi, bool hi_closed,
-                                           int64_t &k0, int64_t &k1) {
-    auto in = [&](int64_t k) {
-        int64_t p = P0 + k * S;
-        return p >= lo && (hi_closed ? p <= hi : p < hi);
-    };
-    if (S == 0) {
-        if (!in(0)) { k0 = 1; k1 = 0; }
-        return;
-    }
-    // first and last k inside, from the FP64 estimate, then exact fix-ups
-    double a = ((double)lo - (double)P0) / (double)S, b = ((double)hi - (double)P0) / (double)S;
-    double kmin = fmin(a, b), kmax = fmax(a, b);
-    int64_t lo_k = (int64_t)fmax(ceil(kmin) - 2.0, (double)k0);
-    int64_t hi_k = (int64_t)fmin(floor(kmax) + 2.0, (double)(k1 - 1));
-    if (lo_k > hi_k) { k0 = 1; k1 = 0; return; }
-    int guard = 0;
-    while (lo_k <= hi_k && !in(lo_k) && guard++ < 8) ++lo_k;
-    guard = 0;
-    while (hi_k >= lo_k && !in(hi_k) && guard++ < 8) --hi_k;
-    if (lo_k > hi_k || !in(lo_k) || !in(hi_k)) { k0 = 1; k1 = 0; return; }
-    k0 = lo_k;
-    k1 = hi_k + 1;
-}
-
 template <typename S, int MODE, int FILTER>
 __global__ __launch_bounds__(256) void k_brick(MarchArgs A, const BrickJob *__restrict__ jobs, int32_t n_jobs) {
     __shared__ float4 lut[1024];
@@ -80,7 +53,7 @@ __global__ __launch_bounds__(256) void k_brick(MarchArgs A, const BrickJob *__re
                 // the cube's outer faces are open-ended (rounding never drops a sample)
                 const int64_t lo_f = bl[a] == 0 ? INT64_MIN / 4 : (int64_t)bl[a] * one;
                 const int64_t hi_f = bh[a] == N[a] ? INT64_MAX / 4 : (int64_t)bh[a] * one;
-                axis_range(P[a], D[a], lo_f, hi_f, false, a0, a1);
+                brick_axis_range(P[a], D[a], lo_f, hi_f, a0, a1);
                 k0 = max(k0, a0);
                 k1 = min(k1, a1);
             }

@@ -548,6 +548,168 @@ __global__ __launch_bounds__(512) void k_slab(SlabArgs SA) {
     slab_bundle<S, MODE, FILTER, ORI>(SA, gbx * SA.bw, gby * SA.bh, smem, red);
 }
 
+// K3 with LDS-staged voxel boxes: one workgroup renders a 16 x 16 tile of one
+// brick's footprint (the same job table as k_brick).  Each lane's ray is set
+// up on the whole cube, and the run of its global samples whose positions
+// lie in the brick (exact fixed-point membership, half-open boxes) is then
+// marched in the brick's own block, as a one-brick volume whose origin is the
+// brick's corner: the slab machinery of the bundle kernel stages the boxes
+// of that block in LDS.  The arithmetic is that of k_brick (same positions,
+// same interpolation and table, the brick's own early stop), so both give
+// the same partials.
+template <typename S, int MODE, int FILTER>
+__global__ __launch_bounds__(256) void k_brick_slab(SlabArgs SA, const BrickJob *__restrict__ jobs, int32_t n_jobs) {
+    extern __shared__ float smem[];
+    __shared__ int32_t red[16];
+    const int32_t t = blockIdx.x;
+    int32_t lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BrickJob J = jobs[lo];
+    const MarchArgs &A = SA.m;
+    const VolDev &Vc = A.vol;                            // the whole bricked cube
+    const int tid = threadIdx.x;
+    const int32_t tl = t - J.tile_begin;
+    const int32_t bx0 = (tl % J.tiles_x) * 16, by0 = (tl / J.tiles_x) * 16;
+    const int32_t lx = bx0 + (tid & 15), ly = by0 + (tid >> 4);
+    const bool valid = lx < J.w && ly < J.h;
+    const int px = J.x0 + lx, py = J.y0 + ly;
+    float4 *lut = (float4 *)smem;
+    float *box = smem + (MODE == VR_COMPOSITE ? 4 * A.lut.n : 0);
+
+    // the brick as a one-brick volume: local voxel (-1,-1,-1) is element 0
+    const int32_t og[3] = {J.bx * Vc.Bx, J.by * Vc.By, J.bz * Vc.Bz};
+    SlabArgs S2 = SA;
+    VolDev &V = S2.m.vol;
+    V.data = J.brick ? J.brick
+                     : (const void *)((const S *)Vc.data +
+                                      ((int64_t)(J.bz * Vc.nby + J.by) * Vc.nbx + J.bx) * Vc.brick_elems);
+    V.nx = Vc.Bx; V.ny = Vc.By; V.nz = Vc.Bz;
+    V.sx = 1; V.sy = Vc.Px; V.sz = Vc.Px * Vc.Py;
+    V.ori = 0; V.single = 1; V.orients = 1;
+
+    Ray r{};
+    if (valid) make_ray(A.cam, Vc, A.cam.tile_x0 + px, A.cam.tile_y0 + py, A.step, r);
+    int64_t P[3], D[3];
+    fix_start(r, A.step, 0, 0.0, P, D);
+    int64_t k0 = 0, k1 = r.n;
+    {
+        const int64_t one = (int64_t)1 << 32;
+        const int32_t bh[3] = {min(og[0] + Vc.Bx, Vc.nx), min(og[1] + Vc.By, Vc.ny), min(og[2] + Vc.Bz, Vc.nz)};
+        const int32_t N[3] = {Vc.nx, Vc.ny, Vc.nz};
+        if (k1 > 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                int64_t a0 = k0, a1 = k1;
+                const int64_t lo_f = og[a] == 0 ? INT64_MIN / 4 : (int64_t)og[a] * one;
+                const int64_t hi_f = bh[a] == N[a] ? INT64_MAX / 4 : (int64_t)bh[a] * one;
+                brick_axis_range(P[a], D[a], lo_f, hi_f, a0, a1);
+                k0 = max(k0, a0);
+                k1 = min(k1, a1);
+            }
+        }
+    }
+    const int64_t sh = FILTER == VR_TRILINEAR ? ((int64_t)1 << 31) : 0;   // corner grid q = p - 1/2
+    LaneState ls;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ls.Q[a] = P[a] - sh + k0 * D[a] - (int64_t)og[a] * ((int64_t)1 << 32);
+        ls.D[a] = D[a];
+    }
+    ls.n = (int32_t)max(k1 - k0, (int64_t)0);
+    ls.k = 0;
+    ls.m = -INFINITY;
+    ls.T = 1.0f;
+    ls.C0 = ls.C1 = ls.C2 = 0.0f;
+    ls.use_log = false;                                  // the brick partial keeps the product, as k_brick does
+    ls.stopped = false;
+
+    // the bundle's slab axis and corner rays, in brick-local coordinates
+    const int cx1 = min(bx0 + 16, J.w) - 1, cy1 = min(by0 + 16, J.h) - 1;
+    double cox[4], coy[4], coz[4], cdx[4], cdy[4], cdz[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        cam_ray(A.cam, A.cam.tile_x0 + J.x0 + ((c & 1) ? cx1 : bx0), A.cam.tile_y0 + J.y0 + ((c & 2) ? cy1 : by0),
+                cox[c], coy[c], coz[c], cdx[c], cdy[c], cdz[c]);
+        cox[c] -= og[0]; coy[c] -= og[1]; coz[c] -= og[2];
+    }
+    const double dcx = cdx[0] + cdx[1] + cdx[2] + cdx[3];
+    const double dcy = cdy[0] + cdy[1] + cdy[2] + cdy[3];
+    const double dcz = cdz[0] + cdz[1] + cdz[2] + cdz[3];
+    int w = 0;
+    if (fabs(dcy) > fabs(dcx)) w = 1;
+    if (fabs(dcz) > fabs(w == 1 ? dcy : dcx)) w = 2;
+    const double dcw = w == 0 ? dcx : (w == 1 ? dcy : dcz);
+    const int sw = dcw > 0 ? 1 : -1;
+    const int u = w == 0 ? 1 : 0, v2 = w == 2 ? 1 : 2;
+    auto pick = [](double x, double y, double z, int ax) -> double { return ax == 0 ? x : (ax == 1 ? y : z); };
+    Frustum F;
+    bool bundle_ok = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double dw = pick(cdx[c], cdy[c], cdz[c], w);
+        if (!(dw * sw >= 0.2)) bundle_ok = false;
+        const double ow = pick(cox[c], coy[c], coz[c], w);
+        const double su = pick(cdx[c], cdy[c], cdz[c], u) / dw, sv = pick(cdx[c], cdy[c], cdz[c], v2) / dw;
+        F.bu[c] = (float)su;
+        F.au[c] = (float)(pick(cox[c], coy[c], coz[c], u) - ow * su);
+        F.bv[c] = (float)sv;
+        F.av[c] = (float)(pick(cox[c], coy[c], coz[c], v2) - ow * sv);
+    }
+    const int32_t N[3] = {V.nx, V.ny, V.nz};
+    F.Nw = w == 0 ? N[0] : (w == 1 ? N[1] : N[2]);
+    F.Nu = u == 0 ? N[0] : N[1];
+    F.Nv = v2 == 1 ? N[1] : N[2];
+    F.h = FILTER == VR_TRILINEAR ? 0.5f : 0.0f;
+    const int64_t Qw0 = w == 0 ? ls.Q[0] : (w == 1 ? ls.Q[1] : ls.Q[2]);
+    const int64_t Dw = w == 0 ? ls.D[0] : (w == 1 ? ls.D[1] : ls.D[2]);
+    const double rdw = w == 0 ? r.dx : (w == 1 ? r.dy : r.dz);
+    const bool reg = valid && ls.n > 0 && bundle_ok && (Dw > 0) == (sw > 0) && fabs(rdw) >= 0.2;
+    int32_t wlo, whi;
+    {
+        const int32_t first = fix_int(Qw0), last = fix_int(Qw0 + (int64_t)(ls.n > 0 ? ls.n - 1 : 0) * Dw);
+        int32_t a = reg ? min(first, last) : INT32_MAX, b = reg ? max(first, last) : INT32_MIN;
+        wg_minmax(a, b, red);
+        wlo = a;
+        whi = b;
+    }
+    if (MODE == VR_COMPOSITE) {
+        for (int i = tid; i < A.lut.n; i += blockDim.x) lut[i] = A.lut.rgba[i];
+        __syncthreads();
+    }
+    if (wlo <= whi && bundle_ok) {
+        if (sw > 0) {
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+            else run_slabs<S, MODE, FILTER, 2, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+        } else {
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+            else run_slabs<S, MODE, FILTER, 2, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+        }
+    }
+    // lanes outside the slab scheme (and any samples left over): direct gathers
+    if (valid && !ls.stopped && ls.k < ls.n) {
+        while (ls.k < ls.n) {
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            if (FILTER == VR_TRILINEAR) { fx = fix_frac(ls.Q[0]); fy = fix_frac(ls.Q[1]); fz = fix_frac(ls.Q[2]); }
+            const float s = gsample<S, FILTER>(V, fix_int(ls.Q[0]), fix_int(ls.Q[1]), fix_int(ls.Q[2]), fx, fy, fz);
+            ls.Q[0] += ls.D[0]; ls.Q[1] += ls.D[1]; ls.Q[2] += ls.D[2];
+            const bool go = consume<MODE>(ls, S2.m, lut, 0, 0, s);
+            ++ls.k;
+            if (!go) break;
+        }
+    }
+    if (valid) {
+        const int64_t o = (int64_t)ly * J.w + lx;
+        if (MODE == VR_MIP) J.data[o] = ls.m;
+        else ((float4 *)J.data)[o] = make_float4(ls.C0, ls.C1, ls.C2, 1.0f - ls.T);
+    }
+}
+
 // K6: persistent workgroups pull bundles from an atomic queue until every
 // bundle of every view is done (each workgroup exits once the counter passes
 // the item count).  Items are numbered view by view, largest views first.
@@ -638,6 +800,47 @@ hipError_t launch_batch(const BatchArgs &a, int32_t mode, int32_t filter, int32_
         case VR_F32: return launch_batch_s<float>(a, mode, filter, groups, s);
         case VR_F16: return launch_batch_s<_Float16>(a, mode, filter, groups, s);
         default: return launch_batch_s<bf16_t>(a, mode, filter, groups, s);
+    }
+}
+
+
+template <typename S, int MODE, int FILTER>
+static hipError_t launch_brick_slab_t(const SlabArgs &a, const BrickJob *jobs, int32_t n, int32_t tiles, size_t lds,
+                                      hipStream_t s) {
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_brick_slab<S, MODE, FILTER>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_brick_slab<S, MODE, FILTER>), dim3((unsigned)tiles), dim3(256), lds, s, a, jobs, n);
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_brick_slab_s(const SlabArgs &a, int32_t mode, int32_t filter, const BrickJob *jobs,
+                                      int32_t n, int32_t tiles, size_t lds, hipStream_t s) {
+    if (mode == VR_MIP) {
+        if (filter == VR_NEAREST) return launch_brick_slab_t<S, VR_MIP, VR_NEAREST>(a, jobs, n, tiles, lds, s);
+        return launch_brick_slab_t<S, VR_MIP, VR_TRILINEAR>(a, jobs, n, tiles, lds, s);
+    }
+    if (filter == VR_NEAREST) return launch_brick_slab_t<S, VR_COMPOSITE, VR_NEAREST>(a, jobs, n, tiles, lds, s);
+    return launch_brick_slab_t<S, VR_COMPOSITE, VR_TRILINEAR>(a, jobs, n, tiles, lds, s);
+}
+
+hipError_t launch_bricks_slab(const MarchArgs &m, int32_t mode, int32_t filter, const BrickJob *jobs_dev,
+                              int32_t n_jobs, int32_t total_tiles, int32_t cap_floats, int32_t lmax, hipStream_t s) {
+    if (n_jobs <= 0 || total_tiles <= 0) return hipSuccess;
+    SlabArgs a{};
+    a.m = m;
+    a.bw = a.bh = 16;
+    const int32_t avail = (160 * 1024 - 1024 - 32 - (mode == VR_COMPOSITE ? m.lut.n * 16 : 0)) / 4;
+    a.cap = cap_floats < avail ? cap_floats : avail;
+    a.lmax = lmax;
+    const size_t lds = (size_t)a.cap * 4 + 32 + (mode == VR_COMPOSITE ? (size_t)m.lut.n * 16 : 0);
+    switch (m.vol.dtype) {
+        case VR_F32: return launch_brick_slab_s<float>(a, mode, filter, jobs_dev, n_jobs, total_tiles, lds, s);
+        case VR_F16: return launch_brick_slab_s<_Float16>(a, mode, filter, jobs_dev, n_jobs, total_tiles, lds, s);
+        default: return launch_brick_slab_s<bf16_t>(a, mode, filter, jobs_dev, n_jobs, total_tiles, lds, s);
     }
 }
 

@@ -74,6 +74,14 @@ std::vector<Foot> footprints(const vr_ctx *ctx) {
 
 int chans(const vr_render_params *p) { return p->mode == VR_MIP ? 1 : 4; }
 
+// K3: direct gathers (tuning path 1) or LDS-staged boxes (otherwise).
+hipError_t launch_k3(const vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, const BrickJob *jobs,
+                     int32_t n, int32_t tiles, hipStream_t s) {
+    if (ctx->tune.path == 1) return launch_bricks(a, p->mode, p->filter, jobs, n, tiles, s);
+    const int32_t kib = (ctx->tune.lds_kib > 0 && ctx->tune.lds_kib <= 144) ? ctx->tune.lds_kib : 64;
+    return launch_bricks_slab(a, p->mode, p->filter, jobs, n, tiles, kib * 1024 / 4, ctx->tune.slab_max, s);
+}
+
 // The brick jobs of one vr_render_bricks call on a streamed volume (jobs in
 // brick-id order, in the pinned staging area, their table not yet copied).
 // Plan on the host which cache slot serves each brick: the bricks already
@@ -135,7 +143,7 @@ int render_streamed(vr_ctx *ctx, const vr_render_params *p, const MarchArgs &a, 
             st.hits++;
         }
         const int32_t tiles = jobs[i].tiles_x * ((jobs[i].h + 15) / 16);
-        if ((e = launch_bricks(a, p->mode, p->filter, dev + i, 1, tiles, s)) != hipSuccess) break;
+        if ((e = launch_k3(ctx, a, p, dev + i, 1, tiles, s)) != hipSuccess) break;
         if ((e = hipEventRecord(st.slot_free[k], s)) != hipSuccess) break;
         st.slot_used[k] = 1;
     }
@@ -204,8 +212,7 @@ int vr_render_bricks(vr_ctx *ctx, const vr_render_params *p, vr_partial *parts, 
     if (ctx->st.on) return render_streamed(ctx, p, a, stage, (int32_t)f.size(), pool, (size_t)tbytes, s);
     hipError_t e = vr_stage_copy(ctx, pool, (size_t)tbytes, s);
     if (e != hipSuccess) return vr_dev_check(ctx, e, "brick table copy");
-    return vr_dev_check(ctx, launch_bricks(a, p->mode, p->filter, (const BrickJob *)pool, (int32_t)f.size(), tiles, s),
-                        "bricks");
+    return vr_dev_check(ctx, launch_k3(ctx, a, p, (const BrickJob *)pool, (int32_t)f.size(), tiles, s), "bricks");
 }
 
 int vr_brick_order(const vr_ctx *ctx, const vr_partial *parts, int32_t n, int32_t *order) {

@@ -232,7 +232,10 @@ __device__ __forceinline__ float gsample(const VolDev &v, int32_t ix, int32_t iy
     return fmaf(fz, y1 - y0, y0);
 }
 
-// Table lookup with linear interpolation; LDS copy of the table.
+// Table lookup with linear interpolation; LDS copy of the table.  A NaN
+// value (a blank voxel in the sample's footprint) is transparent: its
+// opacity is 0, so it adds no colour and leaves the transmittance as it is
+// (the clamp already sends NaN to entry 0, so only alpha needs the select).
 __device__ __forceinline__ float4 lut_eval(const float4 *L, int n, float vmin, float scale, float s) {
     float x = (s - vmin) * scale;
     x = fminf(fmaxf(x, 0.0f), (float)(n - 1));
@@ -243,7 +246,7 @@ __device__ __forceinline__ float4 lut_eval(const float4 *L, int n, float vmin, f
     o.x = fmaf(w, b.x - a.x, a.x);
     o.y = fmaf(w, b.y - a.y, a.y);
     o.z = fmaf(w, b.z - a.z, a.z);
-    o.w = fmaf(w, b.w - a.w, a.w);
+    o.w = s == s ? fmaf(w, b.w - a.w, a.w) : 0.0f;
     return o;
 }
 
@@ -270,6 +273,34 @@ struct LogTrans {
         return __builtin_amdgcn_exp2f(L);
     }
 };
+
+// Samples k in [k0, k1) with lo <= P(k) < hi along one axis, P(k) = P0 + k S
+// (32.32 fixed point): narrows [k0, k1) to them (empty: k0 > k1 - 1).  The
+// brick kernels use it for the exact membership of samples in a brick.
+__device__ __forceinline__ void brick_axis_range(int64_t P0, int64_t S, int64_t lo, int64_t hi, int64_t &k0,
+                                                 int64_t &k1) {
+    auto in = [&](int64_t k) {
+        int64_t p = P0 + k * S;
+        return p >= lo && p < hi;
+    };
+    if (S == 0) {
+        if (!in(0)) { k0 = 1; k1 = 0; }
+        return;
+    }
+    // first and last k inside, from the FP64 estimate, then exact fix-ups
+    double a = ((double)lo - (double)P0) / (double)S, b = ((double)hi - (double)P0) / (double)S;
+    double kmin = fmin(a, b), kmax = fmax(a, b);
+    int64_t lo_k = (int64_t)fmax(ceil(kmin) - 2.0, (double)k0);
+    int64_t hi_k = (int64_t)fmin(floor(kmax) + 2.0, (double)(k1 - 1));
+    if (lo_k > hi_k) { k0 = 1; k1 = 0; return; }
+    int guard = 0;
+    while (lo_k <= hi_k && !in(lo_k) && guard++ < 8) ++lo_k;
+    guard = 0;
+    while (hi_k >= lo_k && !in(hi_k) && guard++ < 8) --hi_k;
+    if (lo_k > hi_k || !in(lo_k) || !in(hi_k)) { k0 = 1; k1 = 0; return; }
+    k0 = lo_k;
+    k1 = hi_k + 1;
+}
 
 // XCD-aware remap: consecutive hardware workgroup ids go round-robin over
 // the 8 XCDs; give each XCD a contiguous range of logical ids so that the

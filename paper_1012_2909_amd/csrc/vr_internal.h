@@ -76,6 +76,10 @@ struct BrickJob {
 };
 hipError_t launch_bricks(const MarchArgs &a, int32_t mode, int32_t filter, const BrickJob *jobs_dev,
                          int32_t n_jobs, int32_t total_tiles, hipStream_t s);
+// K3 with LDS-staged voxel boxes (the bundle kernel's slabs inside each brick);
+// the same partials as launch_bricks.
+hipError_t launch_bricks_slab(const MarchArgs &m, int32_t mode, int32_t filter, const BrickJob *jobs_dev,
+                              int32_t n_jobs, int32_t total_tiles, int32_t cap_floats, int32_t lmax, hipStream_t s);
 
 // K4: composite partials (rectangles in visibility order) into the image.
 struct PartRect {

@@ -205,3 +205,27 @@ def test_over_composite_of_given_partials(R):
     gotm = R.composite_bricks(mparts, order, mode="mip").cpu().numpy()
     assert np.array_equal(gotm, np.max(mfull, axis=0).astype(np.float32))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("brick", [16, 23, 64])
+@pytest.mark.parametrize("cam_name", ["persp", "persp2", "ortho"])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_lds_staged_bricks_equal_direct_gathers(R, brick, cam_name, storage):
+    """K3 with LDS-staged boxes (the default) and K3 with direct gathers
+    (tuning path 1) run the same arithmetic on the same samples: the
+    bricked images are bit-identical, in both modes and both filters."""
+    log(f"case: K3 staged = direct brick={brick} cam={cam_name} {storage}")
+    shape = (64, 40, 48)
+    vol = synth.make_cube(synth.CubeSpec(shape, 10, seed=4, fwhm_z=(4.0, 20.0)))
+    lut = synth.lut_ramp(alpha_scale=0.5)
+    _setup(R, vol, lut, CAMS[cam_name](shape), brick, storage)
+    base = R.get_tuning()
+    for mode, filt in [("composite", "trilinear"), ("composite", "nearest"), ("mip", "trilinear"),
+                       ("mip", "nearest")]:
+        staged = R.render_bricked(mode=mode, filt=filt).cpu().numpy()
+        R.set_tuning(path=1)
+        try:
+            direct = R.render_bricked(mode=mode, filt=filt).cpu().numpy()
+        finally:
+            R.set_tuning(**base)
+        assert np.array_equal(staged, direct), (mode, filt)
