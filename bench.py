@@ -68,9 +68,11 @@ def main():
                     help="cache of the per-angle sample counts and touched blocks ('' for none)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16/BF16-storage, batched and backward variants reported beside the main figure")
-    ap.add_argument("--workload", default="spectral8", choices=["spectral8", "bricked64"],
+    ap.add_argument("--workload", default="spectral8", choices=["spectral8", "bricked64", "deep8", "backward"],
                     help="spectral8: the headline 8 GiB cube at 1920x1080 (default); bricked64: the 64 GiB cube as "
-                         "256^3 bricks, 9600x5400 as 5x5 tiles")
+                         "256^3 bricks, 9600x5400 as 5x5 tiles; deep8: the 8 GiB cube's composite with the alpha/64 "
+                         "ramp alone; backward: forward + adjoint on the 128x128x256 cube at 1024x1024 alone (the "
+                         "last two for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -97,6 +99,9 @@ def main():
         return
     if args.workload == "bricked64":
         run_bricked64(args)
+        return
+    if args.workload in ("deep8", "backward"):
+        run_single(args)
         return
     spec = synth.CUBE_8GIB
     W, H = 1920, 1080
@@ -552,6 +557,49 @@ def run_bricked64(args):
     log(f"cube {synth.CUBE_64GIB.shape} generated in {time.time() - t:.1f}s")
     storages = ["f32", "f16", "bf16"] if args.storage == "all" else [args.storage]
     res = bricked64_measure(vol, storages, max(5, args.steps // 4), args.streamed_slots, log)
+    print(json.dumps(res), flush=True)
+
+
+def run_single(args):
+    """One workload alone, for counter runs: the deep composite of the 8 GiB
+    cube over the 16 angles, or forward + adjoint on the differentiable
+    cube.  Prints one JSON line of its own."""
+    import torch
+    from paper_1012_2909_amd import synth, vr
+    dev = torch.device("cuda", 0)
+    R = vr.Renderer(0)
+    steps = max(1, args.steps)
+    if args.workload == "deep8":
+        spec = synth.CUBE_8GIB
+        vol = synth.make_cube(spec)
+        R.load_volume(torch.from_numpy(vol).to(dev), orientations=3)
+        R.set_lut(synth.lut_ramp(alpha_scale=1.0 / 64.0))
+        cams = [synth.orbit_camera(spec.shape, seed=s, w=1920, h=1080) for s in angle_seeds()]
+        o = torch.empty((1080, 1920, 4), device=dev)
+        ms = []
+        for k in range(steps):
+            R.set_camera(cams[k % N_ANGLES])
+            ms.append(_time_ms(lambda: R.render(out=o), 1))
+        res = {"workload": "8 GiB cube, 1920x1080, ramp alpha/64 composite", "ms_per_frame": ms}
+    else:
+        spec = synth.CUBE_DIFF
+        vol = synth.make_cube(spec)
+        R.load_volume(torch.from_numpy(vol).to(dev), orientations=1)
+        lut = synth.lut_ramp()
+        R.set_lut(lut)
+        R.set_camera(synth.orbit_camera(spec.shape, seed=5, w=1024, h=1024))
+        img, ws = R.render(save=True)
+        gimg = torch.ones_like(img)
+        gl = torch.zeros((lut.table.shape[0], 4), device=dev)
+        gv = torch.zeros(spec.shape, device=dev)
+        ms = []
+        for _ in range(steps):
+            R.render(save=True, workspace=ws, out=img)
+            gl.zero_()
+            gv.zero_()
+            ms.append(_time_ms(lambda: R.render_backward(gimg, ws, gl, gv), 1))
+        res = {"workload": "128x128x256 cube, 1024x1024, forward with checkpoints + adjoint", "backward_ms": ms}
+    R.close()
     print(json.dumps(res), flush=True)
 
 

@@ -124,7 +124,9 @@ typedef struct {
  * 64-lane wave per packet_w x packet_h packet. */
 typedef struct {
     int32_t packet_w, packet_h;   /* pixels per wavefront packet: 8x8, 16x4, 32x2, 64x1, 4x16 */
-    int32_t waves_per_group;      /* 1, 2, 4, 8 (LDS-staged path: 4 or 8) */
+    int32_t waves_per_group;      /* 1, 2, 4, 8 (LDS-staged path: 4 or 8); path 0 renders early-stopping
+                                     composites on one-brick layouts with 1 wave and unroll 1 whatever
+                                     these two fields say (the measured best for rays of a few samples) */
     int32_t unroll;               /* direct path on one-brick layouts: samples per inner iteration, 1, 2, 4 */
     int32_t persistent_groups;    /* batched launch: workgroups per CU; path 3: packets per wave in a
                                      workgroup's share; 1..32 */

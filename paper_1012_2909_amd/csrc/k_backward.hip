@@ -11,10 +11,18 @@
 //   dL/dc_k = gC T_k a_k,   dL/da_k = T_k [gC.(c_k - S) + gA P],
 //   S <- a_k c_k + (1 - a_k) S,   P <- (1 - a_k) P,
 // then chains through the table's linear interpolation (LDS-privatised table
-// gradient, flushed once per workgroup) and the trilinear weights (FP32
-// atomics into the (nz, ny, nx) gradient, corners clamped to the cube as the
-// clamp-to-edge sampling does; a lane sums the contributions of its
-// consecutive samples in one cell before adding them to memory).
+// gradient, flushed once per workgroup) and the trilinear weights (corners
+// clamped to the cube as the clamp-to-edge sampling does; a lane sums the
+// contributions of its consecutive samples in one cell first).
+//
+// Voxel gradients are privatised per workgroup in an LDS cache: a
+// direct-mapped table of kCache voxel slots (tag = voxel index, value = the
+// workgroup's partial sum) filled with an LDS compare-and-swap; a
+// contribution whose slot already holds another voxel goes straight to
+// memory.  The workgroup's rays are neighbours (a compact tile of the image,
+// lanes kStride pixels apart), so they revisit the same voxels many times,
+// and each cached voxel costs one atomic in memory when the workgroup ends
+// instead of one per ray and cell.
 #include "vr_internal.h"
 
 namespace vr {
@@ -22,10 +30,22 @@ namespace vr {
 constexpr int kSeg = 64;        // samples per checkpoint segment
 constexpr int kBackThreads = 128;
 // Lanes of a workgroup take pixels kStride apart in x and y (16 x 8 lanes
-// over a 128 x 64 super-tile; the kStride^2 workgroups of a super-tile take
-// the offsets): neighbouring rays of a dense image share voxels, and lanes of
-// one atomic instruction then rarely hit the same address.
-constexpr int kStride = 8;
+// over a (16 kStride) x (8 kStride) super-tile; the kStride^2 workgroups of a
+// super-tile take the offsets): the workgroup's rays stay close enough to
+// share voxels in its cache, and lanes of one LDS atomic rarely hit the same
+// address.
+constexpr int kStride = 2;
+constexpr int kCache = 4096;    // voxel slots per workgroup (power of two)
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+// Add g to voxel v of the gradient through the workgroup's cache (nv < 2^32
+// - 1 voxels), or straight to memory when v's slot holds another voxel.
+__device__ __forceinline__ void cache_add(uint32_t *tag, float *val, float *gv, uint32_t v, float g) {
+    const uint32_t h = (v * 2654435761u) >> (32 - 12);   // multiplicative hash onto kCache slots
+    const uint32_t old = atomicCAS(&tag[h], kEmpty, v);
+    if (old == kEmpty || old == v) atomicAdd(&val[h], g);
+    else unsafeAtomicAdd(gv + v, g);
+}
 
 __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
     extern __shared__ float smem[];
@@ -34,12 +54,19 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
     float4 *lut = (float4 *)smem;                        // n_l entries
     float *glut = smem + 4 * n_l;                        // n_l * 4 partial gradients
     float *tbuf = glut + 4 * n_l;                        // kSeg x blockDim transmittances
+    uint32_t *ctag = (uint32_t *)(tbuf + kSeg * kBackThreads);   // voxel-gradient cache
+    float *cval = (float *)(ctag + kCache);
     const int tid = threadIdx.x;
     for (int i = tid; i < n_l; i += blockDim.x) {
         lut[i] = A.lut.rgba[i];
         glut[4 * i] = glut[4 * i + 1] = glut[4 * i + 2] = glut[4 * i + 3] = 0.0f;
     }
+    for (int i = tid; i < kCache; i += blockDim.x) {
+        ctag[i] = kEmpty;
+        cval[i] = 0.0f;
+    }
     __syncthreads();
+    const bool cached = (int64_t)A.vol.nx * A.vol.ny * A.vol.nz < (int64_t)kEmpty;
 
     const int64_t npix = (int64_t)A.cam.tile_w * A.cam.tile_h;
     const int32_t sgx = (A.cam.tile_w + 16 * kStride - 1) / (16 * kStride);
@@ -73,14 +100,15 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
             float *gv = B.grad_vol;
             const int64_t r00 = ((int64_t)Z0 * ny + Y0) * nx, r10 = ((int64_t)Z0 * ny + Y1) * nx;
             const int64_t r01 = ((int64_t)Z1 * ny + Y0) * nx, r11 = ((int64_t)Z1 * ny + Y1) * nx;
-            unsafeAtomicAdd(gv + r00 + X0, acc[0]);
-            unsafeAtomicAdd(gv + r00 + X1, acc[1]);
-            unsafeAtomicAdd(gv + r10 + X0, acc[2]);
-            unsafeAtomicAdd(gv + r10 + X1, acc[3]);
-            unsafeAtomicAdd(gv + r01 + X0, acc[4]);
-            unsafeAtomicAdd(gv + r01 + X1, acc[5]);
-            unsafeAtomicAdd(gv + r11 + X0, acc[6]);
-            unsafeAtomicAdd(gv + r11 + X1, acc[7]);
+            const int64_t at[8] = {r00 + X0, r00 + X1, r10 + X0, r10 + X1, r01 + X0, r01 + X1, r11 + X0, r11 + X1};
+            if (cached) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (acc[i] != 0.0f) cache_add(ctag, cval, gv, (uint32_t)at[i], acc[i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) unsafeAtomicAdd(gv + at[i], acc[i]);
+            }
         };
         for (int seg = (m - 1) / kSeg; seg >= 0; --seg) {
             const int k0 = seg * kSeg, k1 = min(k0 + kSeg, m);
@@ -165,13 +193,17 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
         for (int i = tid; i < 4 * n_l; i += blockDim.x)
             if (glut[i] != 0.0f) unsafeAtomicAdd(B.grad_lut + i, glut[i]);
     }
+    if (B.grad_vol && cached) {
+        for (int i = tid; i < kCache; i += blockDim.x)
+            if (ctag[i] != kEmpty && cval[i] != 0.0f) unsafeAtomicAdd(B.grad_vol + ctag[i], cval[i]);
+    }
 }
 
 hipError_t launch_backward(const BackArgs &a, hipStream_t s) {
     const int64_t sgx = (a.m.cam.tile_w + 16 * kStride - 1) / (16 * kStride);
     const int64_t sgy = (a.m.cam.tile_h + 8 * kStride - 1) / (8 * kStride);
     const unsigned blocks = (unsigned)(sgx * sgy * kStride * kStride);
-    const size_t lds = (size_t)a.m.lut.n * 32 + (size_t)kSeg * kBackThreads * 4;
+    const size_t lds = (size_t)a.m.lut.n * 32 + (size_t)kSeg * kBackThreads * 4 + (size_t)kCache * 8;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);

@@ -322,6 +322,16 @@ static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_rend
         int32_t cap = kib * 1024 / 4;
         return launch_slab(a, p->mode, p->filter, a.packet_w, a.packet_h * a.waves, cap, ctx->tune.slab_max, s);
     }
+    if (ctx->tune.path == 0 && ctx->vol.single && p->mode == VR_COMPOSITE) {
+        // the automatic shape of the direct kernel for early-stopping
+        // composites: one wave per workgroup and one sample per iteration
+        // (rays of a few samples each; measured on the 1920x1080 orbit frames
+        // of the 8 GiB cube: 0.21 ms against 0.28 ms with 4 waves and 2)
+        MarchArgs b = a;
+        b.waves = 1;
+        b.unroll = 1;
+        return launch_march(b, p->mode, p->filter, s);
+    }
     return launch_march(a, p->mode, p->filter, s);
 }
 
