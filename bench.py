@@ -67,7 +67,9 @@ def main():
     ap.add_argument("--measure-cache", default="/tmp/vrcube_bench_measure.json",
                     help="cache of the per-angle sample counts and touched blocks ('' for none)")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the FP16/BF16-storage, batched and backward variants reported beside the main figure")
+                    help="skip the FP16/BF16-storage, batched, backward and bricked variants reported beside the main "
+                         "figure")
+    ap.add_argument("--no-bricked", action="store_true", help="skip the bricked 64 GiB variant")
     ap.add_argument("--workload", default="spectral8", choices=["spectral8", "bricked64", "deep8", "backward"],
                     help="spectral8: the headline 8 GiB cube at 1920x1080 (default); bricked64: the 64 GiB cube as "
                          "256^3 bricks, 9600x5400 as 5x5 tiles; deep8: the 8 GiB cube's composite with the alpha/64 "
@@ -241,6 +243,25 @@ def main():
     variants = None
     if not args.no_variants and args.storage == "f32":
         variants = run_variants(R, vol, cams, lut, modes, samples, mean_ms, step)
+    if not args.no_variants and not args.no_bricked and args.storage == "f32":
+        # the bricked 64 GiB cube (FP32, FP16, BF16 storage) and a frame of it
+        # streamed from pinned host memory through a quarter-size brick cache
+        R.storage = None
+        del vol
+        torch.cuda.empty_cache()
+        t = time.time()
+        vol64 = synth.make_cube(synth.CUBE_64GIB)
+        log(f"cube {synth.CUBE_64GIB.shape} generated in {time.time() - t:.1f}s")
+        b64 = bricked64_measure(vol64, ["f32", "f16", "bf16"], 5, streamed_slots=256, log_fn=log)
+        del vol64
+        nvox = 4096 * 2048 * 2048
+        for st, r in b64["storage"].items():
+            esz = 4 if st == "f32" else 2
+            for mode in ("composite", "mip"):
+                alg = nvox * esz + 9600 * 5400 * (16 if mode == "composite" else 4)
+                r[mode]["hbm_roofline_frac"] = round(alg / (r[mode]["ms_per_frame"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        variants = variants or {}
+        variants["bricked_64gib_9600x5400"] = b64
 
     rec = {
         "metric": "G ray-samples/s + fps at 1920x1080 on 8 GiB cube; % HBM roofline",

@@ -322,6 +322,9 @@ def test_low_precision_storage(R, storage):
     # oracle on the FP32 cube measures that part alone
     res = oracle.render(vol, lut, cam, eps_stop=2e-5)
     ref_q = oracle.render(deq, lut, cam, eps_stop=2e-5)
+    # pixels whose early stop lies in its window in either cube are left out:
+    # there the rounding of the stored values can move the stop by one sample,
+    # and the two images then differ by that sample's contribution
     flagged = (res["flags"] != 0) | (ref_q["flags"] != 0)
     mx = float(np.abs(img - res["out"])[~flagged].max())
     quant = float(np.abs(ref_q["out"] - res["out"])[~flagged].max())
@@ -334,6 +337,9 @@ def test_low_precision_storage(R, storage):
         # through the ramp's slope 1/13, and a ray whose transmittance mass
         # sits on such samples sums that error in both alpha and colour
         pytest.xfail(f"BF16 storage misses the 2e-3 bar against the FP32 cube: {mx:.2e}")
+    # the stop flips themselves, counted: pixels flagged in the rounded cube only
+    log(f"{storage}: {int(((ref_q['flags'] != 0) & (res['flags'] == 0)).sum())} px whose stop lies in its window "
+        f"only in the rounded cube")
     assert mx <= TOL_LOWP
 
 
