@@ -115,31 +115,49 @@ __global__ __launch_bounds__(256) void k_brick(MarchArgs A, const BrickJob *__re
 }
 
 // K4: front-to-back "over" of the partial rectangles (already in visibility
-// order) for one 16x16 output tile.
+// order) for one 16x16 output tile.  The rectangles are read 256 at a time;
+// the ones that touch the tile are compacted into LDS in their order (a wave
+// ballot and a prefix over the four waves), so the per-pixel loop runs over
+// the few partials above the tile, not over every brick of the frame.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_over(const PartRect *__restrict__ rects, int32_t n, float *out,
                                               int32_t tile_w, int32_t tile_h) {
     __shared__ PartRect sr[256];
+    __shared__ int32_t wn[4];
+    const int32_t tid = (int32_t)threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t tx0 = blockIdx.x * 16, ty0 = blockIdx.y * 16;
-    const int32_t px = tx0 + (threadIdx.x & 15), py = ty0 + (threadIdx.x >> 4);
+    const int32_t px = tx0 + (tid & 15), py = ty0 + (tid >> 4);
     const bool valid = px < tile_w && py < tile_h;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     float mx = -INFINITY;
     for (int32_t c0 = 0; c0 < n; c0 += 256) {
         const int32_t cn = min(256, n - c0);
+        PartRect R{};
+        bool hit = false;
+        if (tid < cn) {
+            R = rects[c0 + tid];
+            hit = !(R.x0 > tx0 + 15 || R.y0 > ty0 + 15 || R.x0 + R.w <= tx0 || R.y0 + R.h <= ty0);
+        }
+        const uint64_t m = __ballot(hit);
+        __syncthreads();                    // the previous chunk's readers are done with sr and wn
+        if (lane == 0) wn[wv] = __popcll(m);
         __syncthreads();
-        if ((int32_t)threadIdx.x < cn) sr[threadIdx.x] = rects[c0 + threadIdx.x];
+        int32_t base = 0, total = 0;
+#pragma unroll
+        for (int32_t k = 0; k < 4; ++k) {
+            base += k < wv ? wn[k] : 0;
+            total += wn[k];
+        }
+        if (hit) sr[base + __popcll(m & ((1ull << lane) - 1ull))] = R;
         __syncthreads();
-        for (int32_t i = 0; i < cn; ++i) {
-            const PartRect R = sr[i];
-            // uniform rejection of rectangles that miss this output tile
-            if (R.x0 > tx0 + 15 || R.y0 > ty0 + 15 || R.x0 + R.w <= tx0 || R.y0 + R.h <= ty0) continue;
-            if (!valid || px < R.x0 || py < R.y0 || px >= R.x0 + R.w || py >= R.y0 + R.h) continue;
-            const int64_t o = (int64_t)(py - R.y0) * R.w + (px - R.x0);
+        for (int32_t i = 0; i < total; ++i) {
+            const PartRect Q = sr[i];
+            if (!valid || px < Q.x0 || py < Q.y0 || px >= Q.x0 + Q.w || py >= Q.y0 + Q.h) continue;
+            const int64_t o = (int64_t)(py - Q.y0) * Q.w + (px - Q.x0);
             if (MODE == VR_MIP) {
-                mx = fmaxf(mx, R.data[o]);
+                mx = fmaxf(mx, Q.data[o]);
             } else {
-                const float4 p = ((const float4 *)R.data)[o];
+                const float4 p = ((const float4 *)Q.data)[o];
                 const float t = 1.0f - acc.w;
                 acc.x = fmaf(t, p.x, acc.x);
                 acc.y = fmaf(t, p.y, acc.y);

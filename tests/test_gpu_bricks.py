@@ -229,3 +229,22 @@ def test_lds_staged_bricks_equal_direct_gathers(R, brick, cam_name, storage):
         finally:
             R.set_tuning(**base)
         assert np.array_equal(staged, direct), (mode, filt)
+
+
+def test_bricked_full_frame_equals_stitched_panels(R):
+    """The 5x5 wall rendered in one bricked call equals its 25 panels
+    rendered one by one and stitched, bit for bit (each panel is a window of
+    the same frame; each brick's partial covers its footprint in either)."""
+    shape = (60, 36, 46)
+    vol = synth.make_cube(synth.CubeSpec(shape, 10, seed=3, fwhm_z=(4.0, 20.0)))
+    lut = synth.lut_ramp(alpha_scale=1 / 8)
+    frame = synth.orbit_camera(shape, seed=21, w=160, h=90)
+    _setup(R, vol, lut, frame, 16)
+    for mode in ("composite", "mip"):
+        full = R.render_bricked(mode=mode).cpu().numpy()
+        for cam in synth.tiles_5x5(frame, 32, 18):
+            R.set_camera(cam)
+            x0, y0, w, h = cam.tile
+            part = R.render_bricked(mode=mode).cpu().numpy()
+            assert np.array_equal(part, full[y0:y0 + h, x0:x0 + w]), (mode, cam.tile)
+        R.set_camera(frame)
