@@ -61,6 +61,11 @@ extern "C" {
 
 typedef struct vr_ctx vr_ctx;
 
+/* A render saved for the adjoint (save_for_backward) keeps, per pixel, the
+ * transmittance in front of every VR_CHECKPOINT_INTERVAL-th sample of the
+ * ray; the adjoint replays that many samples from a checkpoint. */
+#define VR_CHECKPOINT_INTERVAL 8
+
 typedef enum {
     VR_OK = 0,
     VR_EINVAL = -1,       /* bad argument */
@@ -254,7 +259,9 @@ int vr_set_camera(vr_ctx *ctx, const vr_camera *cam);
 
 /* Workspace bytes vr_render needs for these params with the current camera,
  * volume and launch shape: samples taken and transmittance checkpoints when
- * save_for_backward; 64 bytes per pixel of ray records when the view is
+ * save_for_backward (int32 per pixel, then from the next 256-byte boundary
+ * ceil(max samples / VR_CHECKPOINT_INTERVAL) float planes of one value per
+ * pixel); 64 bytes per pixel of ray records when the view is
  * rendered in object order (MIP, path 4 or the automatic choice); else 0.
  * With a smaller workspace an object-order view is rendered by the bundle
  * kernels instead (the same image). */

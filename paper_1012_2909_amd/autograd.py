@@ -2,9 +2,9 @@
 forward and adjoint kernels.
 
 The forward pass renders the composite image and keeps, per pixel, only the
-number of samples taken and the transmittance at every 64th sample; the
-backward pass replays each 64-sample segment from its checkpoint and
-accumulates gradients with respect to the transfer-function table and the
+number of samples taken and the transmittance at every 8th sample
+(vr.CHECKPOINT_INTERVAL); the backward pass replays each segment from its
+checkpoint and accumulates gradients with respect to the transfer-function table and the
 voxels.  Both run in the library's kernels; this module only marshals
 tensors.
 """

@@ -3,31 +3,35 @@
 //
 // The forward pass (k_march / k_slab with save_for_backward) stored, per
 // pixel, the number of samples taken m and the transmittance in front of
-// samples 0, 64, 128, ... (segment checkpoints), so no per-sample state is
-// kept.  Here one lane owns one ray and walks its segments from the last to
-// the first: it replays the segment forward from its checkpoint (writing T_k
-// into LDS), then walks it backwards carrying the suffix sums
+// samples 0, kCkpt, 2 kCkpt, ... (segment checkpoints), so no per-sample
+// state is kept.  Here one lane owns one ray and walks its segments from the
+// last to the first: it replays the kCkpt samples of a segment forward from
+// the checkpoint into registers (the transmittance in front of each sample
+// and the sample value, with the forward's own arithmetic), then walks them
+// backwards carrying the suffix sums
 //   S (colour behind the sample, as seen from it) and P (transmittance behind):
 //   dL/dc_k = gC T_k a_k,   dL/da_k = T_k [gC.(c_k - S) + gA P],
 //   S <- a_k c_k + (1 - a_k) S,   P <- (1 - a_k) P,
 // then chains through the table's linear interpolation (LDS-privatised table
 // gradient, flushed once per workgroup) and the trilinear weights (corners
 // clamped to the cube as the clamp-to-edge sampling does; a lane sums the
-// contributions of its consecutive samples in one cell first).
+// contributions of its consecutive samples in one cell first).  Each sample
+// is gathered once; the only LDS are the table, its gradient and the voxel
+// cache below, which keeps several workgroups per CU to hide the gathers.
 //
 // Voxel gradients are privatised per workgroup in an LDS cache: a
 // direct-mapped table of kCache voxel slots (tag = voxel index, value = the
-// workgroup's partial sum) filled with an LDS compare-and-swap; a
-// contribution whose slot already holds another voxel goes straight to
-// memory.  The workgroup's rays are neighbours (a compact tile of the image,
-// lanes kStride pixels apart), so they revisit the same voxels many times,
-// and each cached voxel costs one atomic in memory when the workgroup ends
-// instead of one per ray and cell.
+// workgroup's partial sum); an empty slot is claimed with an LDS
+// compare-and-swap, and a contribution whose slot already holds another
+// voxel goes straight to memory.  The workgroup's rays are neighbours (a
+// compact tile of the image, lanes kStride pixels apart), so they revisit the
+// same voxels many times, and each cached voxel costs one atomic in memory
+// when the workgroup ends instead of one per ray and cell.
 #include "vr_internal.h"
 
 namespace vr {
 
-constexpr int kSeg = 64;        // samples per checkpoint segment
+constexpr int kSeg = kCkpt;     // samples per checkpoint segment, replayed into registers
 constexpr int kBackThreads = 128;
 // Lanes of a workgroup take pixels kStride apart in x and y (16 x 8 lanes
 // over a (16 kStride) x (8 kStride) super-tile; the kStride^2 workgroups of a
@@ -35,15 +39,22 @@ constexpr int kBackThreads = 128;
 // share voxels in its cache, and lanes of one LDS atomic rarely hit the same
 // address.
 constexpr int kStride = 2;
-constexpr int kCache = 4096;    // voxel slots per workgroup (power of two)
+constexpr int kCache = 2048;    // voxel slots per workgroup (power of two; 16 KiB of LDS)
+constexpr int kCacheBits = __builtin_ctz(kCache);
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 // Add g to voxel v of the gradient through the workgroup's cache (nv < 2^32
 // - 1 voxels), or straight to memory when v's slot holds another voxel.
 __device__ __forceinline__ void cache_add(uint32_t *tag, float *val, float *gv, uint32_t v, float g) {
-    const uint32_t h = (v * 2654435761u) >> (32 - 12);   // multiplicative hash onto kCache slots
-    const uint32_t old = atomicCAS(&tag[h], kEmpty, v);
-    if (old == kEmpty || old == v) atomicAdd(&val[h], g);
+    const uint32_t h = (v * 2654435761u) >> (32 - kCacheBits);   // multiplicative hash onto kCache slots
+    // a slot's tag is set once and never changes: a plain read settles hits
+    // and misses on a taken slot, the compare-and-swap only claims an empty one
+    uint32_t t = __hip_atomic_load(&tag[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (t == kEmpty) {
+        const uint32_t old = atomicCAS(&tag[h], kEmpty, v);
+        t = old == kEmpty ? v : old;
+    }
+    if (t == v) atomicAdd(&val[h], g);
     else unsafeAtomicAdd(gv + v, g);
 }
 
@@ -53,8 +64,7 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
     const int n_l = A.lut.n;
     float4 *lut = (float4 *)smem;                        // n_l entries
     float *glut = smem + 4 * n_l;                        // n_l * 4 partial gradients
-    float *tbuf = glut + 4 * n_l;                        // kSeg x blockDim transmittances
-    uint32_t *ctag = (uint32_t *)(tbuf + kSeg * kBackThreads);   // voxel-gradient cache
+    uint32_t *ctag = (uint32_t *)(glut + 4 * n_l);      // voxel-gradient cache
     float *cval = (float *)(ctag + kCache);
     const int tid = threadIdx.x;
     for (int i = tid; i < n_l; i += blockDim.x) {
@@ -72,7 +82,7 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
     const int32_t sgx = (A.cam.tile_w + 16 * kStride - 1) / (16 * kStride);
     const int32_t st = (int32_t)blockIdx.x / (kStride * kStride), sub = (int32_t)blockIdx.x % (kStride * kStride);
     const int px = (st % sgx) * 16 * kStride + sub % kStride + kStride * (tid % 16);
-    const int py = (st / sgx) * 8 * kStride + sub / kStride + kStride * (tid / 16);
+    const int py = (st / sgx) * (kBackThreads / 16) * kStride + sub / kStride + kStride * (tid / 16);
     const bool inside = px < A.cam.tile_w && py < A.cam.tile_h;
     const int64_t pix = (int64_t)py * A.cam.tile_w + px;
     const VolDev &V = A.vol;
@@ -111,79 +121,89 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
             }
         };
         for (int seg = (m - 1) / kSeg; seg >= 0; --seg) {
-            const int k0 = seg * kSeg, k1 = min(k0 + kSeg, m);
-            // forward replay of the segment from its checkpoint
-            float T = A.ckpt[(int64_t)seg * npix + pix];
-            LogTrans lt;
-            if (use_log) lt.L = T > 0.0f ? __builtin_amdgcn_logf(T) : -INFINITY;
-            int64_t q0 = Q0[0] + (int64_t)k0 * D[0], q1 = Q0[1] + (int64_t)k0 * D[1], q2 = Q0[2] + (int64_t)k0 * D[2];
-            for (int k = k0; k < k1; ++k) {
-                tbuf[(k - k0) * blockDim.x + tid] = T;
-                const float s = gsample<float, VR_TRILINEAR>(V, fix_int(q0), fix_int(q1), fix_int(q2), fix_frac(q0),
+            {
+                // replay of the segment from its checkpoint into registers
+                // (transmittance in front of each sample and the sample value),
+                // then the backward sweep over it
+                const int j0 = seg * kSeg, nj = min(kSeg, m - j0);
+                float Tj = A.ckpt[(int64_t)seg * npix + pix];
+                LogTrans lj;
+                if (use_log) lj.L = Tj > 0.0f ? __builtin_amdgcn_logf(Tj) : -INFINITY;
+                float Ts[kSeg], ss[kSeg];
+                int64_t q0 = Q0[0] + (int64_t)j0 * D[0], q1 = Q0[1] + (int64_t)j0 * D[1],
+                        q2 = Q0[2] + (int64_t)j0 * D[2];
+#pragma unroll
+                for (int i = 0; i < kSeg; ++i) {
+                    if (i < nj) {
+                        Ts[i] = Tj;
+                        ss[i] = gsample<float, VR_TRILINEAR>(V, fix_int(q0), fix_int(q1), fix_int(q2), fix_frac(q0),
                                                              fix_frac(q1), fix_frac(q2));
-                const float a = lut_eval(lut, n_l, A.lut.vmin, A.lut.scale, s).w;
-                T = use_log ? lt.step(a) : T - T * a;
-                q0 += D[0]; q1 += D[1]; q2 += D[2];
-            }
-            // reverse sweep
-            for (int k = k1 - 1; k >= k0; --k) {
-                q0 -= D[0]; q1 -= D[1]; q2 -= D[2];
-                const int ix = fix_int(q0), iy = fix_int(q1), iz = fix_int(q2);
-                const float fx = fix_frac(q0), fy = fix_frac(q1), fz = fix_frac(q2);
-                const float s = gsample<float, VR_TRILINEAR>(V, ix, iy, iz, fx, fy, fz);
-                // table entry and slope
-                float x = (s - A.lut.vmin) * A.lut.scale;
-                const bool clamped = !(x > 0.0f && x < (float)(n_l - 1));
-                x = fminf(fmaxf(x, 0.0f), (float)(n_l - 1));
-                const int j = min((int)x, n_l - 2);
-                const float w = x - (float)j;
-                const float4 La = lut[j], Lb = lut[j + 1];
-                const bool blank = !(s == s);              // NaN: transparent, uses no table entry
-                const float c0 = fmaf(w, Lb.x - La.x, La.x), c1 = fmaf(w, Lb.y - La.y, La.y);
-                const float c2 = fmaf(w, Lb.z - La.z, La.z), a = blank ? 0.0f : fmaf(w, Lb.w - La.w, La.w);
-                const float Tk = tbuf[(k - k0) * blockDim.x + tid];
-                const float ta = Tk * a;
-                const float d0 = g.x * ta, d1 = g.y * ta, d2 = g.z * ta;
-                const float da = Tk * (g.x * (c0 - S0) + g.y * (c1 - S1) + g.z * (c2 - S2) + g.w * P);
-                // table gradient (LDS-privatised)
-                if (B.grad_lut && !blank) {
-                    const float wa = 1.0f - w;
-                    atomicAdd(&glut[4 * j + 0], wa * d0);
-                    atomicAdd(&glut[4 * j + 1], wa * d1);
-                    atomicAdd(&glut[4 * j + 2], wa * d2);
-                    atomicAdd(&glut[4 * j + 3], wa * da);
-                    atomicAdd(&glut[4 * j + 4], w * d0);
-                    atomicAdd(&glut[4 * j + 5], w * d1);
-                    atomicAdd(&glut[4 * j + 6], w * d2);
-                    atomicAdd(&glut[4 * j + 7], w * da);
-                }
-                // value gradient through the table, then the trilinear weights
-                if (B.grad_vol && !clamped) {
-                    const float gs = (d0 * (Lb.x - La.x) + d1 * (Lb.y - La.y) + d2 * (Lb.z - La.z) +
-                                      da * (Lb.w - La.w)) * A.lut.scale;
-                    if (gs != 0.0f) {
-                        if (ix != cx || iy != cy || iz != cz) {
-                            flush();
-                            cx = ix; cy = iy; cz = iz;
-                            for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
-                        }
-                        const float wx1 = fx, wx0 = 1.0f - fx, wy1 = fy, wy0 = 1.0f - fy, wz1 = fz, wz0 = 1.0f - fz;
-                        const float g00 = gs * wz0 * wy0, g10 = gs * wz0 * wy1;
-                        const float g01 = gs * wz1 * wy0, g11 = gs * wz1 * wy1;
-                        acc[0] = fmaf(g00, wx0, acc[0]);
-                        acc[1] = fmaf(g00, wx1, acc[1]);
-                        acc[2] = fmaf(g10, wx0, acc[2]);
-                        acc[3] = fmaf(g10, wx1, acc[3]);
-                        acc[4] = fmaf(g01, wx0, acc[4]);
-                        acc[5] = fmaf(g01, wx1, acc[5]);
-                        acc[6] = fmaf(g11, wx0, acc[6]);
-                        acc[7] = fmaf(g11, wx1, acc[7]);
+                        const float a = lut_eval(lut, n_l, A.lut.vmin, A.lut.scale, ss[i]).w;
+                        Tj = use_log ? lj.step(a) : Tj - Tj * a;
+                        q0 += D[0]; q1 += D[1]; q2 += D[2];
                     }
                 }
-                S0 = fmaf(a, c0 - S0, S0);
-                S1 = fmaf(a, c1 - S1, S1);
-                S2 = fmaf(a, c2 - S2, S2);
-                P = P - a * P;
+#pragma unroll
+                for (int i = kSeg - 1; i >= 0; --i) {
+                    if (i >= nj) continue;
+                    q0 -= D[0]; q1 -= D[1]; q2 -= D[2];
+                    const int ix = fix_int(q0), iy = fix_int(q1), iz = fix_int(q2);
+                    const float fx = fix_frac(q0), fy = fix_frac(q1), fz = fix_frac(q2);
+                    const float s = ss[i];
+                    // table entry and slope
+                    float x = (s - A.lut.vmin) * A.lut.scale;
+                    const bool clamped = !(x > 0.0f && x < (float)(n_l - 1));
+                    x = fminf(fmaxf(x, 0.0f), (float)(n_l - 1));
+                    const int j = min((int)x, n_l - 2);
+                    const float w = x - (float)j;
+                    const float4 La = lut[j], Lb = lut[j + 1];
+                    const bool blank = !(s == s);              // NaN: transparent, uses no table entry
+                    const float c0 = fmaf(w, Lb.x - La.x, La.x), c1 = fmaf(w, Lb.y - La.y, La.y);
+                    const float c2 = fmaf(w, Lb.z - La.z, La.z), a = blank ? 0.0f : fmaf(w, Lb.w - La.w, La.w);
+                    const float Tk = Ts[i];
+                    const float ta = Tk * a;
+                    const float d0 = g.x * ta, d1 = g.y * ta, d2 = g.z * ta;
+                    const float da = Tk * (g.x * (c0 - S0) + g.y * (c1 - S1) + g.z * (c2 - S2) + g.w * P);
+                    // table gradient (LDS-privatised)
+                    if (B.grad_lut && !blank) {
+                        const float wa = 1.0f - w;
+                        atomicAdd(&glut[4 * j + 0], wa * d0);
+                        atomicAdd(&glut[4 * j + 1], wa * d1);
+                        atomicAdd(&glut[4 * j + 2], wa * d2);
+                        atomicAdd(&glut[4 * j + 3], wa * da);
+                        atomicAdd(&glut[4 * j + 4], w * d0);
+                        atomicAdd(&glut[4 * j + 5], w * d1);
+                        atomicAdd(&glut[4 * j + 6], w * d2);
+                        atomicAdd(&glut[4 * j + 7], w * da);
+                    }
+                    // value gradient through the table, then the trilinear weights
+                    if (B.grad_vol && !clamped) {
+                        const float gs = (d0 * (Lb.x - La.x) + d1 * (Lb.y - La.y) + d2 * (Lb.z - La.z) +
+                                          da * (Lb.w - La.w)) * A.lut.scale;
+                        if (gs != 0.0f) {
+                            if (ix != cx || iy != cy || iz != cz) {
+                                flush();
+                                cx = ix; cy = iy; cz = iz;
+                                for (int i2 = 0; i2 < 8; ++i2) acc[i2] = 0.0f;
+                            }
+                            const float wx1 = fx, wx0 = 1.0f - fx, wy1 = fy, wy0 = 1.0f - fy, wz1 = fz, wz0 = 1.0f - fz;
+                            const float g00 = gs * wz0 * wy0, g10 = gs * wz0 * wy1;
+                            const float g01 = gs * wz1 * wy0, g11 = gs * wz1 * wy1;
+                            acc[0] = fmaf(g00, wx0, acc[0]);
+                            acc[1] = fmaf(g00, wx1, acc[1]);
+                            acc[2] = fmaf(g10, wx0, acc[2]);
+                            acc[3] = fmaf(g10, wx1, acc[3]);
+                            acc[4] = fmaf(g01, wx0, acc[4]);
+                            acc[5] = fmaf(g01, wx1, acc[5]);
+                            acc[6] = fmaf(g11, wx0, acc[6]);
+                            acc[7] = fmaf(g11, wx1, acc[7]);
+                        }
+                    }
+                    S0 = fmaf(a, c0 - S0, S0);
+                    S1 = fmaf(a, c1 - S1, S1);
+                    S2 = fmaf(a, c2 - S2, S2);
+                    P = P - a * P;
+                }
             }
         }
         if (B.grad_vol) flush();
@@ -201,9 +221,9 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
 
 hipError_t launch_backward(const BackArgs &a, hipStream_t s) {
     const int64_t sgx = (a.m.cam.tile_w + 16 * kStride - 1) / (16 * kStride);
-    const int64_t sgy = (a.m.cam.tile_h + 8 * kStride - 1) / (8 * kStride);
+    const int64_t sgy = (a.m.cam.tile_h + (kBackThreads / 16) * kStride - 1) / ((kBackThreads / 16) * kStride);
     const unsigned blocks = (unsigned)(sgx * sgy * kStride * kStride);
-    const size_t lds = (size_t)a.m.lut.n * 32 + (size_t)kSeg * kBackThreads * 4 + (size_t)kCache * 8;
+    const size_t lds = (size_t)a.m.lut.n * 32 + (size_t)kCache * 8;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_backward, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);

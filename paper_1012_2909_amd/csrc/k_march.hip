@@ -116,7 +116,7 @@ __global__ __launch_bounds__(512) void k_march(MarchArgs A) {
         if (MODE == VR_MIP) {
             m = fmaxf(m, s);
         } else {
-            if (A.ckpt && (k & 63) == 0 && (k >> 6) < A.ckpt_segs) A.ckpt[(int64_t)(k >> 6) * A.cam.tile_w * A.cam.tile_h + pix] = T;
+            if (A.ckpt && (k & (kCkpt - 1)) == 0 && (k >> kCkptShift) < A.ckpt_segs) A.ckpt[(int64_t)(k >> kCkptShift) * A.cam.tile_w * A.cam.tile_h + pix] = T;
             float4 c = lut_eval(lut, A.lut.n, A.lut.vmin, A.lut.scale, s);
             float ta = T * c.w;
             C0 = fmaf(ta, c.x, C0);
@@ -168,8 +168,8 @@ __device__ __forceinline__ void march_u_run(const MarchArgs &A, const float4 *lu
             if (MODE == VR_MIP) {
                 m = fmaxf(m, s);
             } else {
-                if (A.ckpt && ((k + j) & 63) == 0 && ((k + j) >> 6) < A.ckpt_segs)
-                    A.ckpt[(int64_t)((k + j) >> 6) * npix + pix] = T;
+                if (A.ckpt && ((k + j) & (kCkpt - 1)) == 0 && ((k + j) >> kCkptShift) < A.ckpt_segs)
+                    A.ckpt[(int64_t)((k + j) >> kCkptShift) * npix + pix] = T;
                 float4 c = lut_eval(lut, A.lut.n, A.lut.vmin, A.lut.scale, s);
                 float ta = T * c.w;
                 C0 = fmaf(ta, c.x, C0);
@@ -309,8 +309,8 @@ __global__ __launch_bounds__(256) void k_march_c(CompactArgs C) {
             if (MODE == VR_MIP) {
                 m = fmaxf(m, s);
             } else {
-                if (A.ckpt && ((k + j) & 63) == 0 && ((k + j) >> 6) < A.ckpt_segs)
-                    A.ckpt[(int64_t)((k + j) >> 6) * npix + pix] = T;
+                if (A.ckpt && ((k + j) & (kCkpt - 1)) == 0 && ((k + j) >> kCkptShift) < A.ckpt_segs)
+                    A.ckpt[(int64_t)((k + j) >> kCkptShift) * npix + pix] = T;
                 float4 c = lut_eval(lut, A.lut.n, A.lut.vmin, A.lut.scale, s);
                 float ta = T * c.w;
                 C0 = fmaf(ta, c.x, C0);

@@ -147,7 +147,7 @@ __device__ __forceinline__ bool consume(LaneState &L, const MarchArgs &A, const 
         L.m = r;
         return true;
     }
-    if (A.ckpt && (L.k & 63) == 0 && (L.k >> 6) < A.ckpt_segs) A.ckpt[(int64_t)(L.k >> 6) * npix + pix] = L.T;
+    if (A.ckpt && (L.k & (kCkpt - 1)) == 0 && (L.k >> kCkptShift) < A.ckpt_segs) A.ckpt[(int64_t)(L.k >> kCkptShift) * npix + pix] = L.T;
     float4 c = lut_eval(lut, A.lut.n, A.lut.vmin, A.lut.scale, s);
     float ta = L.T * c.w;
     L.C0 = fmaf(ta, c.x, L.C0);

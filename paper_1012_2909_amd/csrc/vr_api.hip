@@ -535,7 +535,7 @@ int vr_set_camera(vr_ctx *ctx, const vr_camera *cam) {
 // render
 // ---------------------------------------------------------------------------
 static int64_t ckpt_segs(const vr_ctx *ctx, const vr_render_params *p) {
-    return (max_samples(ctx->vol, p->step) + 63) / 64;
+    return (max_samples(ctx->vol, p->step) + vr::kCkpt - 1) / vr::kCkpt;
 }
 
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }

@@ -6,6 +6,13 @@
 
 namespace vr {
 
+// Transmittance checkpoints of a render saved for the adjoint: one before
+// every kCkpt-th sample of a ray.  The adjoint replays kCkpt samples from a
+// checkpoint into registers, so the interval is also its register budget.
+constexpr int kCkptShift = 3;
+constexpr int kCkpt = 1 << kCkptShift;
+static_assert(kCkpt == VR_CHECKPOINT_INTERVAL, "checkpoint interval of the ABI");
+
 struct MarchArgs {
     CamDev cam;
     VolDev vol;
@@ -15,7 +22,7 @@ struct MarchArgs {
     int32_t ert;          // early termination enabled
     void *out;            // float4 (composite) / float (MIP) per tile pixel, or NULL
     int32_t *counts;      // samples taken per pixel, or NULL
-    float *ckpt;          // transmittance before samples 0, 64, 128, ... (segment-major), or NULL
+    float *ckpt;          // transmittance before samples 0, kCkpt, 2 kCkpt, ... (segment-major), or NULL
     int32_t *taken;       // samples taken per pixel (for the adjoint), or NULL
     int32_t ckpt_segs;    // checkpoints per pixel
     int32_t trans;        // 0 product, 1 log, 2 per-ray choice (log when n > 1024)

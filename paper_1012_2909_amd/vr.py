@@ -22,6 +22,7 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 MODES = {"composite": 0, "mip": 1}
 FILTERS = {"trilinear": 0, "nearest": 1}
 TRANS = {"auto": 0, "product": 1, "log": 2}
+CHECKPOINT_INTERVAL = 8     # VR_CHECKPOINT_INTERVAL of include/vr.h
 
 
 class Camera(C.Structure):

@@ -33,6 +33,12 @@ def test_every_declared_function_is_exported():
     assert sorted(n for n, _, _ in vr.SIGNATURES) == names
 
 
+def test_checkpoint_interval_matches_header():
+    from paper_1012_2909_amd import vr
+    src = open(os.path.join(ROOT, "include", "vr.h")).read()
+    assert int(re.search(r"#define VR_CHECKPOINT_INTERVAL (\d+)", src).group(1)) == vr.CHECKPOINT_INTERVAL
+
+
 def test_version():
     vr, L = _lib()
     assert b"gfx950" in L.vr_version()

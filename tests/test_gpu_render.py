@@ -352,7 +352,8 @@ def _saved(ws, npix, segs):
     off = (npix * 4 + 255) // 256 * 256
     taken = ws[:npix * 4].view(torch.int32).cpu().numpy().copy()
     ck = ws[off:off + segs * npix * 4].view(torch.float32).cpu().numpy().reshape(segs, npix).copy()
-    written = np.arange(segs)[:, None] * 64 < taken[None, :]
+    from paper_1012_2909_amd import vr
+    written = np.arange(segs)[:, None] * vr.CHECKPOINT_INTERVAL < taken[None, :]
     return taken, np.where(written, ck, 0.0)
 
 
