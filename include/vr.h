@@ -251,7 +251,7 @@ int vr_stream_stats(const vr_ctx *ctx, int64_t *bricks_copied, int64_t *cache_hi
  * vr_render's automatic path; the images do not depend on it. */
 int vr_set_transfer_function(vr_ctx *ctx, const float *rgba_dev, int32_t n, float vmin, float vmax);
 
-/* ---- camera (section 3: same orientation, user-defined output size) ----- */
+/* ---- camera (section 3: a static render keeps the view and takes a new output size) */
 
 int vr_set_camera(vr_ctx *ctx, const vr_camera *cam);
 
@@ -339,9 +339,9 @@ int vr_render_backward(vr_ctx *ctx, const vr_render_params *params, const float 
                        const void *workspace_dev, int64_t ws_bytes, float *grad_lut_dev,
                        float *grad_vol_dev, void *stream);
 
-/* ---- depth and catalogue overlay (section 2: a source finder's catalogue
- *      of detected sources, each a bounding cube, drawn as wireframe boxes
- *      over the rendering and following the view) ----------------------- */
+/* ---- depth and catalogue overlay (section 2: the box around each source
+ *      of a detection catalogue is outlined on top of the rendered image
+ *      and moves with the view) ------------------------------------------ */
 
 /* One catalogue entry: the axis-aligned box [lo, hi] in voxel coordinates of
  * the cube (world units; a source covering voxels i0..i1 along an axis spans

@@ -7,10 +7,10 @@
  * calls it.
  *
  * What it computes: the ray-casting volume rendering the paper's framework
- * performs on spectral cubes (abstract and section 1: "real-time interactive
- * volume rendering ... using the ray-casting algorithm"; section 3: a static
- * render of the same orientation at a user-defined output size, and a 5x5
- * wall of 1920x1080 panels).  The paper gives no formulas, so every rule
+ * performs on spectral cubes (abstract and section 1: interactive rendering
+ * of the cube by GPU ray casting; section 3: a static render of the current
+ * view at an output size the user picks, and a 5x5 wall of 1920x1080
+ * panels).  The paper gives no formulas, so every rule
  * below is a stated reading, chosen so that a test can pin it:
  *
  *  World      voxel units; the cube occupies [0,nx]x[0,ny]x[0,nz]; voxel

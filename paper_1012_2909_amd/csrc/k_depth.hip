@@ -1,7 +1,7 @@
 // k_depth.hip -- per-pixel depth of a render and the catalogue overlay that
-// is drawn against it (section 2: a source finder's catalogue, the bounding
-// cube of every detected source, superimposed as wireframe boxes on the
-// volume rendering, following the view).
+// is drawn against it (section 2: the box around each detected source of a
+// catalogue is outlined on top of the rendered image and moves with the
+// view).
 //
 // Depth (K9, one-brick layouts): the ray parameter t of one sample per pixel,
 //  - composite: the first sample after which the accumulated opacity reaches
