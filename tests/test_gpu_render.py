@@ -488,3 +488,37 @@ def test_object_order_workspace_and_fallback(R, cube64):
         assert np.array_equal(R.render(mode="mip").cpu().numpy(), ref)
     finally:
         R.set_tuning(**base_t)
+
+
+def test_layout_grids_past_65535_planes(R):
+    """A cube of 70000 planes along z: K0 writes copy 0 and the transposed
+    copies in launches of at most 65535 planes each (a grid dimension's
+    limit); every copy, forced in turn, renders the same image bit for bit,
+    and it matches the oracle (composite, nearest MIP bit-exact)."""
+    log("case: 70000x2x3 cube, orthographic view along x, copies 0..2 forced")
+    shape = (70000, 2, 3)
+    rng = np.random.default_rng(31)
+    vol = rng.standard_normal(shape).astype(np.float32) * 3.0
+    lut = synth.lut_ramp()
+    # looking along +x; image right is -z, so rows cross all 70000 planes
+    cam = synth.Camera(synth.ORTHO, (-1.0, 1.0, 35000.0), (0.0, 1.0, 35000.0), (0.0, -1.0, 0.0),
+                       half_w=35000.0, half_h=1.0, full_w=512, full_h=4)
+    base_t = R.get_tuning()
+    try:
+        R.load_volume(torch.from_numpy(vol), orientations=3)
+        R.set_lut(lut)
+        R.set_camera(cam)
+        imgs = {}
+        for mode, filt in (("composite", "trilinear"), ("mip", "nearest")):
+            got = []
+            for c in (0, 1, 2):
+                R.set_tuning(**{**base_t, "path": 1, "copy": c})
+                got.append(R.render(mode=mode, filt=filt).cpu().numpy())
+            assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[2]), mode
+            imgs[mode] = got[0]
+    finally:
+        R.set_tuning(**base_t)
+    res = oracle.render(vol, lut, cam, eps_stop=2e-5)
+    assert_accept(imgs["composite"], res, TOL_COMPOSITE, what="70000-plane composite")
+    resm = oracle.render(vol, lut, cam, mode="mip", filt="nearest")
+    assert_bitexact_mip(imgs["mip"], resm, "70000-plane nearest MIP")
