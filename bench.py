@@ -28,6 +28,35 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-instruction
+# slot per lane and clock (a wave64 instruction takes 4 clocks of a SIMD;
+# the 157.3 TFLOP/s FP32 figure counts packed FMAs, two flops each, twice this)
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def stored_valu(key):
+    """VALU lane-instruction slots per sample measured by the counters in
+    profiles/traffic.json for this kernel revision, or None."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        v = json.load(open(tf)).get("valu")
+        if v and v.get("kernel_rev") == kernel_revision():
+            return float(v[key])
+    except (OSError, ValueError, KeyError, TypeError):
+        pass
+    return None
+
+
+def valu_ceiling(key, samples, ms):
+    """The ALU side of a kernel's roofline: counted VALU work over its time
+    against VALU_PEAK (None without counters for this revision)."""
+    per = stored_valu(key)
+    if per is None:
+        return None
+    achieved = per * samples / (ms * 1e-3)
+    return {"bound": "alu", "achieved": round(achieved / 1e12, 2), "peak": round(VALU_PEAK / 1e12, 2),
+            "unit": "T VALU lane-instructions/s", "frac": round(achieved / VALU_PEAK, 4),
+            "valu_per_sample": per}
 N_ANGLES = 16
 
 
@@ -236,6 +265,10 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname[dom],
             "algorithmic_bytes_per_launch": int(alg_per_launch)}
+    valu_roof = None
+    if dom == "mip" and args.storage == "f32" and tunes["mip"]["path"] == 0:
+        valu_roof = valu_ceiling("mip_f32", float(np.mean([samples["mip"][k % N_ANGLES] for k in range(args.steps)])),
+                                 mean_ms["mip"])
 
     cpu = None
     if not args.no_cpu:
@@ -260,6 +293,9 @@ def main():
             for mode in ("composite", "mip"):
                 alg = nvox * esz + 9600 * 5400 * (16 if mode == "composite" else 4)
                 r[mode]["hbm_roofline_frac"] = round(alg / (r[mode]["ms_per_frame"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                if st == "f32":
+                    r[mode]["valu_ceiling_k3"] = valu_ceiling(f"bricked64_f32_{mode}", r[mode]["samples_per_frame"],
+                                                              r[mode]["ms_per_frame"])
         variants = variants or {}
         variants["bricked_64gib_9600x5400"] = b64
 
@@ -290,6 +326,7 @@ def main():
         "launch_shapes": tunes,
         "load_volume": {"ms": round(load_ms, 3), "GBps_moved": round(load_gbs, 1)},
         "roofline": roof,
+        "valu_ceiling": valu_roof,
         "cpu_baseline": cpu,
         "variants": variants,
     }
