@@ -72,7 +72,7 @@ typedef enum {
     VR_ESTATE = -2,       /* call made in the wrong state (e.g. render before load) */
     VR_ENOMEM = -3,       /* caller's buffer or workspace too small */
     VR_EDEVICE = -4,      /* HIP error */
-    VR_EUNSUPPORTED = -5  /* valid but not supported by this build */
+    VR_EUNSUPPORTED = -5  /* valid but not supported by the library */
 } vr_status;
 
 typedef enum { VR_F32 = 0, VR_F16 = 1, VR_BF16 = 2 } vr_dtype;
