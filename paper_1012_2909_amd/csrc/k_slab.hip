@@ -421,11 +421,38 @@ __device__ __forceinline__ void run_slabs(const SlabArgs &SA, const Frustum &F, 
     }
 }
 
+// The lanes whose pixel (px, py) is a corner of the bundle [bx0, cx1] x
+// [by0, cy1] store their ray (origin minus (sx, sy, sz), direction); then a
+// barrier.  A lane may hold several corners of a one-pixel-wide bundle.
+__device__ __forceinline__ void publish_corners(double *corners, int px, int py, int bx0, int by0, int cx1, int cy1,
+                                                const Ray &r, double sx, double sy, double sz) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (px == ((c & 1) ? cx1 : bx0) && py == ((c & 2) ? cy1 : by0)) {
+            double *q = corners + 6 * c;
+            q[0] = r.ox - sx; q[1] = r.oy - sy; q[2] = r.oz - sz;
+            q[3] = r.dx; q[4] = r.dy; q[5] = r.dz;
+        }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void read_corners(const double *corners, double (&ox)[4], double (&oy)[4],
+                                             double (&oz)[4], double (&dx)[4], double (&dy)[4], double (&dz)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double *q = corners + 6 * c;
+        ox[c] = q[0]; oy[c] = q[1]; oz[c] = q[2];
+        dx[c] = q[3]; dy[c] = q[4]; dz[c] = q[5];
+    }
+}
+
 // One bundle of bw x bh pixels whose top-left pixel is (bx0, by0) of the
 // viewport in SA.m (called by every thread of the workgroup).  smem holds the
-// table (composite) followed by the voxel box; red is a 16-int scratch.
+// table (composite) followed by the voxel box; red is a 16-int scratch and
+// corners a 24-double one.
 template <typename S, int MODE, int FILTER, int ORI>
-__device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0, float *smem, int32_t *red) {
+__device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0, float *smem, int32_t *red,
+                                            double *corners) {
     const MarchArgs &A = SA.m;
     const int tid = threadIdx.x;
     float4 *lut = (float4 *)smem;                               // composite: n entries
@@ -449,11 +476,11 @@ __device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0
 
     // ---- the bundle's slab axis and corner rays (uniform) -----------------
     const int cx1 = min(bx0 + SA.bw, A.cam.tile_w) - 1, cy1 = min(by0 + SA.bh, A.cam.tile_h) - 1;
+    // the corner rays are the rays of the lanes at the bundle's corner pixels
+    // (all inside the viewport), shared through LDS
+    publish_corners(corners, px, py, bx0, by0, cx1, cy1, r, 0.0, 0.0, 0.0);
     double cox[4], coy[4], coz[4], cdx[4], cdy[4], cdz[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        cam_ray(A.cam, A.cam.tile_x0 + ((c & 1) ? cx1 : bx0), A.cam.tile_y0 + ((c & 2) ? cy1 : by0), cox[c], coy[c],
-                coz[c], cdx[c], cdy[c], cdz[c]);
+    read_corners(corners, cox, coy, coz, cdx, cdy, cdz);
     const double dcx = cdx[0] + cdx[1] + cdx[2] + cdx[3];
     const double dcy = cdy[0] + cdy[1] + cdy[2] + cdy[3];
     const double dcz = cdz[0] + cdz[1] + cdz[2] + cdz[3];
@@ -542,10 +569,11 @@ template <typename S, int MODE, int FILTER, int ORI>
 __global__ __launch_bounds__(512) void k_slab(SlabArgs SA) {
     extern __shared__ float smem[];
     __shared__ int32_t red[16];
+    __shared__ double corners[24];
     int32_t gbx, gby;
     tile_xy(blockIdx.x, gridDim.x, SA.m.groups_x, (int32_t)(gridDim.x / (uint32_t)SA.m.groups_x), SA.m.order, gbx,
             gby);
-    slab_bundle<S, MODE, FILTER, ORI>(SA, gbx * SA.bw, gby * SA.bh, smem, red);
+    slab_bundle<S, MODE, FILTER, ORI>(SA, gbx * SA.bw, gby * SA.bh, smem, red, corners);
 }
 
 // K3 with LDS-staged voxel boxes: one workgroup renders a 16 x 16 tile of one
@@ -561,6 +589,7 @@ template <typename S, int MODE, int FILTER>
 __global__ __launch_bounds__(256) void k_brick_slab(SlabArgs SA, const BrickJob *__restrict__ jobs, int32_t n_jobs) {
     extern __shared__ float smem[];
     __shared__ int32_t red[16];
+    __shared__ double corners[24];
     const int32_t t = blockIdx.x;
     int32_t lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -629,13 +658,11 @@ __global__ __launch_bounds__(256) void k_brick_slab(SlabArgs SA, const BrickJob 
 
     // the bundle's slab axis and corner rays, in brick-local coordinates
     const int cx1 = min(bx0 + 16, J.w) - 1, cy1 = min(by0 + 16, J.h) - 1;
+    // the corner rays (in brick-local coordinates) are the rays of the lanes at
+    // the tile's corner pixels, shared through LDS
+    publish_corners(corners, lx, ly, bx0, by0, cx1, cy1, r, (double)og[0], (double)og[1], (double)og[2]);
     double cox[4], coy[4], coz[4], cdx[4], cdy[4], cdz[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        cam_ray(A.cam, A.cam.tile_x0 + J.x0 + ((c & 1) ? cx1 : bx0), A.cam.tile_y0 + J.y0 + ((c & 2) ? cy1 : by0),
-                cox[c], coy[c], coz[c], cdx[c], cdy[c], cdz[c]);
-        cox[c] -= og[0]; coy[c] -= og[1]; coz[c] -= og[2];
-    }
+    read_corners(corners, cox, coy, coz, cdx, cdy, cdz);
     const double dcx = cdx[0] + cdx[1] + cdx[2] + cdx[3];
     const double dcy = cdy[0] + cdy[1] + cdy[2] + cdy[3];
     const double dcz = cdz[0] + cdz[1] + cdz[2] + cdz[3];
@@ -717,6 +744,7 @@ template <typename S, int MODE, int FILTER>
 __global__ __launch_bounds__(512) void k_batch(BatchArgs B) {
     extern __shared__ float smem[];
     __shared__ int32_t red[16];
+    __shared__ double corners[24];
     __shared__ int32_t item_s;
     for (;;) {
         if (threadIdx.x == 0) item_s = (int32_t)atomicAdd(B.queue, 1u);
@@ -755,9 +783,9 @@ __global__ __launch_bounds__(512) void k_batch(BatchArgs B) {
         SA.lmax = B.lmax;
         const int32_t t = item - V.tile_begin;
         const int bx0 = (t % V.tiles_x) * B.bw, by0 = (t / V.tiles_x) * B.bh;
-        if (V.ori == 1) slab_bundle<S, MODE, FILTER, 1>(SA, bx0, by0, smem, red);
-        else if (V.ori == 2) slab_bundle<S, MODE, FILTER, 2>(SA, bx0, by0, smem, red);
-        else slab_bundle<S, MODE, FILTER, 0>(SA, bx0, by0, smem, red);
+        if (V.ori == 1) slab_bundle<S, MODE, FILTER, 1>(SA, bx0, by0, smem, red, corners);
+        else if (V.ori == 2) slab_bundle<S, MODE, FILTER, 2>(SA, bx0, by0, smem, red, corners);
+        else slab_bundle<S, MODE, FILTER, 0>(SA, bx0, by0, smem, red, corners);
         __syncthreads();   // the table and box in LDS are rewritten by the next item
     }
 }
