@@ -15,7 +15,9 @@
 // then chains through the table's linear interpolation (LDS-privatised table
 // gradient, flushed once per workgroup) and the trilinear weights (corners
 // clamped to the cube as the clamp-to-edge sampling does; a lane sums the
-// contributions of its consecutive samples in one cell first).  Each sample
+// contributions of its consecutive samples in one cell first, and when the
+// ray steps into a neighbouring cell the four sums of the shared face stay in
+// registers).  Each sample
 // is gathered once; the only LDS are the table, its gradient and the voxel
 // cache below, which keeps several workgroups per CU to hide the gathers.
 //
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
         // step is half a voxel: a cell holds two or three samples of a ray)
         int32_t cx = INT32_MIN, cy = 0, cz = 0;
         float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        auto flush = [&]() {
+        auto flush = [&](uint32_t keep) {
             if (cx == INT32_MIN) return;
             const int X0 = min(max(cx, 0), nx - 1), X1 = min(max(cx + 1, 0), nx - 1);
             const int Y0 = min(max(cy, 0), ny - 1), Y1 = min(max(cy + 1, 0), ny - 1);
@@ -114,11 +116,40 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
             if (cached) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    if (acc[i] != 0.0f) cache_add(ctag, cval, gv, (uint32_t)at[i], acc[i]);
+                    if (!((keep >> i) & 1u) && acc[i] != 0.0f) cache_add(ctag, cval, gv, (uint32_t)at[i], acc[i]);
             } else {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) unsafeAtomicAdd(gv + at[i], acc[i]);
+                for (int i = 0; i < 8; ++i)
+                    if (!((keep >> i) & 1u)) unsafeAtomicAdd(gv + at[i], acc[i]);
             }
+        };
+        // corner i of a cell is (x, y, z) offset (i & 1, (i >> 1) & 1, i >> 2).
+        // Moving to the next cell along one axis keeps the shared face's four
+        // sums in registers: they carry over to the new cell's opposite face,
+        // and only the other four leave.
+        auto move_cell = [&](int ix, int iy, int iz) {
+            int axis = -1, dir = 0;
+            if (cx != INT32_MIN) {
+                const int ddx = ix - cx, ddy = iy - cy, ddz = iz - cz;
+                if (ddy == 0 && ddz == 0 && (ddx == 1 || ddx == -1)) { axis = 0; dir = ddx; }
+                else if (ddx == 0 && ddz == 0 && (ddy == 1 || ddy == -1)) { axis = 1; dir = ddy; }
+                else if (ddx == 0 && ddy == 0 && (ddz == 1 || ddz == -1)) { axis = 2; dir = ddz; }
+            }
+            // the kept face: the far one (bit set) when moving up, else the near one
+            const uint32_t face[3][2] = {{0x55u, 0xAAu}, {0x33u, 0xCCu}, {0x0Fu, 0xF0u}};
+            flush(axis < 0 ? 0u : face[axis][dir > 0 ? 1 : 0]);
+            auto carry = [&](int lo_i, int hi_i, bool up) {   // corners differing in the axis bit
+                if (up) { acc[lo_i] = acc[hi_i]; acc[hi_i] = 0.0f; }
+                else { acc[hi_i] = acc[lo_i]; acc[lo_i] = 0.0f; }
+            };
+            if (axis == 0) { carry(0, 1, dir > 0); carry(2, 3, dir > 0); carry(4, 5, dir > 0); carry(6, 7, dir > 0); }
+            else if (axis == 1) { carry(0, 2, dir > 0); carry(1, 3, dir > 0); carry(4, 6, dir > 0); carry(5, 7, dir > 0); }
+            else if (axis == 2) { carry(0, 4, dir > 0); carry(1, 5, dir > 0); carry(2, 6, dir > 0); carry(3, 7, dir > 0); }
+            else {
+#pragma unroll
+                for (int i2 = 0; i2 < 8; ++i2) acc[i2] = 0.0f;
+            }
+            cx = ix; cy = iy; cz = iz;
         };
         for (int seg = (m - 1) / kSeg; seg >= 0; --seg) {
             {
@@ -181,11 +212,7 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
                         const float gs = (d0 * (Lb.x - La.x) + d1 * (Lb.y - La.y) + d2 * (Lb.z - La.z) +
                                           da * (Lb.w - La.w)) * A.lut.scale;
                         if (gs != 0.0f) {
-                            if (ix != cx || iy != cy || iz != cz) {
-                                flush();
-                                cx = ix; cy = iy; cz = iz;
-                                for (int i2 = 0; i2 < 8; ++i2) acc[i2] = 0.0f;
-                            }
+                            if (ix != cx || iy != cy || iz != cz) move_cell(ix, iy, iz);
                             const float wx1 = fx, wx0 = 1.0f - fx, wy1 = fy, wy0 = 1.0f - fy, wz1 = fz, wz0 = 1.0f - fz;
                             const float g00 = gs * wz0 * wy0, g10 = gs * wz0 * wy1;
                             const float g01 = gs * wz1 * wy0, g11 = gs * wz1 * wy1;
@@ -206,7 +233,7 @@ __global__ __launch_bounds__(kBackThreads) void k_backward(BackArgs B) {
                 }
             }
         }
-        if (B.grad_vol) flush();
+        if (B.grad_vol) flush(0u);
     }
     __syncthreads();
     if (B.grad_lut) {
