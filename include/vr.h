@@ -168,6 +168,16 @@ int vr_destroy(vr_ctx *ctx);
 const char *vr_last_error(const vr_ctx *ctx);
 const char *vr_version(void);
 
+/* Debug builds (every source compiled with -DVR_DEBUG_BOUNDS; the build
+ * writes them as libvrcube_debug.so) check the index range of every direct
+ * gather from the volume (padded indices within [0, N + 1]) and of every
+ * read of an LDS-staged voxel box, and count violations in a 4-byte device
+ * counter the context allocates (the only other allocation of a context).
+ * This call waits for the device, returns the count since the previous call
+ * and resets it.  Release builds: VR_EUNSUPPORTED.  Host-only context:
+ * VR_EDEVICE. */
+int64_t vr_debug_bounds_violations(vr_ctx *ctx);
+
 /* ---- volume (section 1: cubes larger than one machine's memory are
  *      handled as bricks; section 3: float32 cubes such as HIPASS) -------- */
 

@@ -210,9 +210,9 @@ struct BlockLoad {
 };
 
 // Largest of the samples [kb, ke) of ray R in the LDS box of block lo.
-template <int FILTER, int BY>
-__device__ __forceinline__ float block_max(const RayRec &R, int32_t kb, int32_t ke, const int32_t lo[3],
-                                           const float *box) {
+template <int FILTER, int BY, int BZ>
+__device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int32_t kb, int32_t ke,
+                                           const int32_t lo[3], const float *box) {
     constexpr uint32_t bM = 4u * kPX, bS = 4u * kPX * (BY + 1);
     int64_t q0 = R.Q[0] + (int64_t)kb * R.D[0];
     int64_t q1 = R.Q[1] + (int64_t)kb * R.D[1];
@@ -221,6 +221,8 @@ __device__ __forceinline__ float block_max(const RayRec &R, int32_t kb, int32_t 
     float m = -INFINITY;
     for (int32_t k = kb; k < ke; ++k) {
         const int32_t ix = fix_int(q0) - lo[0], iy = fix_int(q1) - lo[1], iz = fix_int(q2) - lo[2];
+        // the box holds corner offsets [0, kBX] x [0, BY] x [0, BZ]: a sample's low corner is inside the block
+        VR_BOUNDS(V, ix >= 0 && iy >= 0 && iz >= 0 && ix < kBX && iy < BY && iz < BZ);
         const uint32_t o = (uint32_t)(ix + __mul24(iy, kPX) + __mul24(iz, kPX * (BY + 1))) << 2;
         float s;
         if (FILTER == VR_NEAREST) {
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(NT) void k_mip_blocks(BlockArgs B) {
             if (i != tid) R = B.tab[pix];
             int32_t kb, ke;
             block_run(R, lo, hi, kb, ke);
-            if (kb < ke) atomicMax(out + pix, mip_enc(block_max<FILTER, BY>(R, kb, ke, lo, box)));
+            if (kb < ke) atomicMax(out + pix, mip_enc(block_max<FILTER, BY, BZ>(V, R, kb, ke, lo, box)));
         }
         R = Rn;
         t = tn;

@@ -196,6 +196,7 @@ __device__ __forceinline__ void lds_samples(LaneState &ls, const MarchArgs &A, c
         const int32_t ib = ORI == 0 ? i1 : (ORI == 1 ? i2 : i0);
         const int32_t ic = ORI == 0 ? i2 : (ORI == 1 ? i0 : i1);
         const int32_t off = ia + __mul24(ib, esm) + __mul24(ic, ess) + base;
+        VR_BOUNDS(A.vol, (uint32_t)off <= maxoff);   // the clamp below never engages
         const uint32_t o = min((uint32_t)off, maxoff) << 2;
         float s;
         if (FILTER == VR_NEAREST) {

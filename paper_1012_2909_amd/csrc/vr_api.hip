@@ -363,6 +363,13 @@ int vr_create(vr_ctx **out, int device) {
     vr_ctx *c = new (std::nothrow) vr_ctx();
     if (!c) return fail(nullptr, VR_ENOMEM, "out of host memory");
     c->device = device;
+#ifdef VR_DEBUG_BOUNDS
+    if (hipMalloc((void **)&c->dbg, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->dbg, 0, sizeof(uint32_t)) != hipSuccess) {
+        delete c;
+        return fail(nullptr, VR_EDEVICE, "debug build: cannot allocate the bounds counter");
+    }
+#endif
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
@@ -380,8 +387,24 @@ int vr_destroy(vr_ctx *ctx) {
     if (ctx->stage_pending) (void)hipEventSynchronize(ctx->stage_done);
     if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
+    if (ctx->dbg) (void)hipFree(ctx->dbg);
     delete ctx;
     return VR_OK;
+}
+
+int64_t vr_debug_bounds_violations(vr_ctx *ctx) {
+    if (!ctx) return fail(nullptr, VR_EINVAL, "context is NULL");
+#ifdef VR_DEBUG_BOUNDS
+    if (ctx->device < 0 || !ctx->dbg) return fail(ctx, VR_EDEVICE, "host-only context");
+    uint32_t n = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&n, ctx->dbg, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(ctx->dbg, 0, sizeof(uint32_t));
+    if (e != hipSuccess) return fail(ctx, VR_EDEVICE, "bounds counter: %s", hipGetErrorString(e));
+    return (int64_t)n;
+#else
+    return fail(ctx, VR_EUNSUPPORTED, "a release build: index-range checks need a build with VR_DEBUG_BOUNDS");
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -458,6 +481,7 @@ int vr_describe_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz, int32_t 
     if (dst_bytes < need) return fail(ctx, VR_ENOMEM, "destination holds %lld bytes, layout needs %lld",
                                       (long long)dst_bytes, (long long)need);
     v.data = dst_dev;
+    v.dbg = ctx->dbg;
     vr_stream_reset(ctx);
     ctx->vol = v;
     ctx->has_volume = true;

@@ -48,7 +48,24 @@ struct VolDev {
     int32_t orients;      // copies stored (1 or 3)
     int32_t pad;
     int64_t copy_off[3];  // element offset of each copy from the layout base
+    uint32_t *dbg;        // debug builds: device counter of index-range violations (else NULL)
 };
+
+// Debug builds (compiled with VR_DEBUG_BOUNDS) check the index range of every
+// direct gather and every LDS box read and count violations in the
+// context's device counter (VolDev::dbg) instead of trusting the geometry;
+// vr_debug_bounds_violations reads the count.  Release builds compile the
+// checks away.
+#ifdef VR_DEBUG_BOUNDS
+#define VR_BOUNDS(v, cond)                                        \
+    do {                                                          \
+        if (!(cond) && (v).dbg) atomicAdd((v).dbg, 1u);           \
+    } while (0)
+#else
+#define VR_BOUNDS(v, cond) \
+    do {                   \
+    } while (0)
+#endif
 
 // Padded extents of copy c of a one-brick layout: the fastest axis c rounded
 // up to a multiple of 8 elements, the other two n + 2.
@@ -219,6 +236,9 @@ template <typename S, int FILTER>
 __device__ __forceinline__ float gsample(const VolDev &v, int32_t ix, int32_t iy, int32_t iz, float fx, float fy,
                                          float fz) {
     const uint32_t sx = (uint32_t)v.sx, sy = (uint32_t)v.sy, sz = (uint32_t)v.sz;
+    // padded indices i + 1 (and i + 2 for the trilinear's upper corner) lie in [0, N + 1]
+    VR_BOUNDS(v, ix >= -1 && iy >= -1 && iz >= -1 && ix + (FILTER == VR_TRILINEAR) <= v.nx &&
+                     iy + (FILTER == VR_TRILINEAR) <= v.ny && iz + (FILTER == VR_TRILINEAR) <= v.nz);
     const S *p = (const S *)v.data + ((uint32_t)(ix + 1) * sx + (uint32_t)(iy + 1) * sy + (uint32_t)(iz + 1) * sz);
     if (FILTER == VR_NEAREST) return Store<S>::ld(p);
     float c000 = Store<S>::ld(p), c100 = Store<S>::ld(p + sx);

@@ -57,6 +57,7 @@ struct vr_ctx {
     std::vector<int64_t> graph_key;
     hipStream_t capture_stream = nullptr;
     int32_t cus = 256;    // compute units of the device
+    uint32_t *dbg = nullptr;   // debug builds: the index-range violation counter (device memory)
     int32_t graph_captures = 0;
     vr_stream_state st;   // out-of-core bricks (off unless vr_describe_streamed_volume)
 };

@@ -144,6 +144,7 @@ int vr_describe_streamed_volume(vr_ctx *ctx, int64_t nx, int64_t ny, int64_t nz,
         st.slot_ready.push_back(b);
     }
     v.data = cache_dev;
+    v.dbg = ctx->dbg;
     ctx->vol = v;
     ctx->has_volume = true;
     ctx->vol_loaded = true;            // the bricks are packed already

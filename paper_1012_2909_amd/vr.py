@@ -61,6 +61,7 @@ SIGNATURES = [
     ("vr_create", C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     ("vr_destroy", C.c_int, [P]),
     ("vr_last_error", C.c_char_p, [P]),
+    ("vr_debug_bounds_violations", C.c_int64, [P]),
     ("vr_version", C.c_char_p, []),
     ("vr_volume_bytes", I64, [I64, I64, I64, I32, I32, I32]),
     ("vr_load_volume", C.c_int, [P, P, I64, I64, I64, I32, I32, I32, P, I64, P]),
@@ -225,6 +226,11 @@ class Renderer:
         if self.ctx:
             lib().vr_destroy(self.ctx)
             self.ctx = None
+
+    def debug_bounds_violations(self):
+        """Index-range violations counted since the last call (debug library
+        only; a release library raises VRError with VR_EUNSUPPORTED)."""
+        return int(self._check(lib().vr_debug_bounds_violations(self.ctx)))
 
     def __del__(self):
         try:
