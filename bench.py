@@ -99,11 +99,13 @@ def main():
                     help="skip the FP16/BF16-storage, batched, backward and bricked variants reported beside the main "
                          "figure")
     ap.add_argument("--no-bricked", action="store_true", help="skip the bricked 64 GiB variant")
-    ap.add_argument("--workload", default="spectral8", choices=["spectral8", "bricked64", "deep8", "backward"],
+    ap.add_argument("--workload", default="spectral8", choices=["spectral8", "bricked64", "deep8", "backward",
+                                                                "choices"],
                     help="spectral8: the headline 8 GiB cube at 1920x1080 (default); bricked64: the 64 GiB cube as "
                          "256^3 bricks, the 9600x5400 frame of the 5x5 wall; deep8: the 8 GiB cube's composite with the alpha/64 "
-                         "ramp alone; backward: forward + adjoint on the 128x128x256 cube at 1024x1024 alone (the "
-                         "last two for counter runs)")
+                         "ramp alone; backward: forward + adjoint on the 128x128x256 cube at 1024x1024 alone; "
+                         "choices: the 8 GiB frames under each design choice and its alternative, one render per case "
+                         "and angle (the last three for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -133,6 +135,9 @@ def main():
         return
     if args.workload in ("deep8", "backward"):
         run_single(args)
+        return
+    if args.workload == "choices":
+        run_choices(args)
         return
     spec = synth.CUBE_8GIB
     W, H = 1920, 1080
@@ -609,6 +614,60 @@ def run_bricked64(args):
     storages = ["f32", "f16", "bf16"] if args.storage == "all" else [args.storage]
     res = bricked64_measure(vol, storages, max(5, args.steps // 4), args.streamed_slots, log)
     print(json.dumps(res), flush=True)
+
+
+# Design choices and their alternatives on the 8 GiB cube (mode, what, tuning):
+# LDS-staged voxel boxes against direct gathers, the orientation copy chosen per
+# view against copy 0 alone, and for early-stopping composites fixed 16x4 ray
+# packets against one-row packets and against ballot compaction of finished
+# rays.  Every case is one kernel per frame.
+CHOICES = [
+    ("mip", "LDS-staged voxel boxes, automatic copy (k_slab)", dict(path=2)),
+    ("mip", "direct gathers, automatic copy (k_march_u)", dict(path=1)),
+    ("mip", "LDS-staged voxel boxes, x-fastest copy forced (k_slab)", dict(path=2, copy=0)),
+    ("composite", "16x4 ray packets (k_march_u)", dict(path=1)),
+    ("composite", "64x1 ray packets (k_march_u)", dict(path=1, packet_w=64, packet_h=1)),
+    ("composite", "16x4 packets with ballot compaction of finished rays (k_march_c)", dict(path=3)),
+]
+CHOICE_ANGLES = 4
+
+
+def run_choices(args):
+    """One render per (case, angle) in CHOICES order on the first
+    CHOICE_ANGLES angles -- the order the counter passes see the kernels in --
+    then timed repeats and the sample counts.  Prints one JSON line."""
+    import torch
+    from paper_1012_2909_amd import synth, vr
+    dev = torch.device("cuda", 0)
+    spec = synth.CUBE_8GIB
+    vol = synth.make_cube(spec)
+    R = vr.Renderer(0)
+    R.load_volume(torch.from_numpy(vol).to(dev), orientations=3)
+    del vol
+    R.set_lut(synth.lut_ramp())
+    cams = [synth.orbit_camera(spec.shape, seed=s, w=1920, h=1080) for s in angle_seeds()[:CHOICE_ANGLES]]
+    base = R.get_tuning()
+    outs = {m: torch.empty((1080, 1920) if m == "mip" else (1080, 1920, 4), device=dev) for m in ("mip", "composite")}
+    for mode, _, tune in CHOICES:              # the counted renders, in order
+        R.set_tuning(**{**base, **tune})
+        for cam in cams:
+            R.set_camera(cam)
+            R.render(mode=mode, out=outs[mode])
+    torch.cuda.synchronize()
+    res = []
+    for mode, what, tune in CHOICES:
+        R.set_tuning(**{**base, **tune})
+        ms, n = [], 0
+        for cam in cams:
+            R.set_camera(cam)
+            ms.append(_time_ms(lambda: R.render(mode=mode, out=outs[mode]), max(1, args.steps // 4)))
+            n += int(R.count_samples(mode=mode).to(torch.int64).sum().item())
+        res.append({"mode": mode, "case": what, "tuning": tune, "ms_per_frame": [round(x, 3) for x in ms],
+                    "samples": n})
+    R.set_tuning(**base)
+    R.close()
+    print(json.dumps({"workload": f"8 GiB cube, 1920x1080, first {CHOICE_ANGLES} orbit angles", "cases": res}),
+          flush=True)
 
 
 def run_single(args):
