@@ -262,7 +262,7 @@ def main():
         except (OSError, ValueError, KeyError):
             traffic = None
     mip_kernels = {0: "MIP frame: k_slab (ray bundles), or k_raytable + k_mip_blocks + k_mip_decode (object order) "
-                      "on views oblique to all three axes",
+                      "on views oblique to the axes",
                    1: "k_march<MIP>", 2: "k_slab<MIP>", 3: "k_march_c<MIP>",
                    4: "k_raytable + k_mip_blocks + k_mip_decode"}
     kname = {"mip": mip_kernels.get(tunes["mip"]["path"], "MIP"),

@@ -142,10 +142,10 @@ typedef struct {
                                      4 MIP in object order: blocks of the volume in LDS, one atomic maximum per
                                      pixel and block (one-brick layouts, MIP only; needs the per-pixel ray
                                      records vr_render_workspace_bytes counts, else renders as path 0).
-                                     Path 4 reads lds_kib 8..63 as 32x16x16 blocks (else 32x32x16),
+                                     Path 4 reads lds_kib 64..144 as 32x32x16 blocks (else 32x16x16),
                                      waves_per_group 8 as 512 threads on the larger blocks, slab_max as the
                                      blocks each workgroup walks along x.  Path 0 takes path 4 for MIP views
-                                     oblique to all three axes (lds_kib 0 and waves_per_group >= 4) */
+                                     oblique to the axes (lds_kib 0 and waves_per_group >= 4) */
     int32_t lds_kib;              /* LDS-staged path: voxel-box budget per workgroup, 8..144 KiB;
                                      0 = per view: 144 KiB for views oblique to all three axes, else 64 */
     int32_t slab_max;             /* LDS-staged path: thickest slab tried, 1..64 voxels */

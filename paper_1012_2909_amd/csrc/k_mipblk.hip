@@ -44,6 +44,19 @@ static_assert(sizeof(RayRec) == 64, "ray record is one 64-byte line");
 
 constexpr int kBX = 32;                          // block edge along x (corner indices)
 constexpr int kPX = 36;                          // LDS row pitch (floats): kBX + 1 rounded up to 4
+constexpr int kMaxRun = 64;                      // blocks along x per workgroup
+
+// Waves per SIMD that the kernel's registers are budgeted for.  A CU has
+// four SIMDs and 160 KiB of LDS; a 256-thread workgroup puts one wave on each
+// SIMD, so the budget matches the number of workgroups the LDS of a block of
+// BY x BZ rows leaves room for (the voxel box, its spare slot and the run's
+// rectangles; at most 4), and registers do not cut the occupancy below what
+// the LDS allows.  Other workgroup sizes keep two waves per SIMD (the FP32
+// staging of a 512-thread group does not fit the 128 registers of four).
+template <int BY, int BZ, int NT> constexpr int waves_per_simd() {
+    constexpr int bytes = 4 * (kPX * (BY + 1) * (BZ + 1) + 8) + kMaxRun * 16;
+    return NT != 256 ? 2 : (163840 / bytes < 4 ? 163840 / bytes : 4);
+}
 
 // Order-preserving map of a (non-NaN) float onto uint32 and back.
 __device__ __forceinline__ uint32_t mip_enc(float f) {
@@ -133,17 +146,6 @@ __device__ __forceinline__ void block_rect(const CamDev &c, const VolDev &v, con
     if (y1 < y0) y1 = y0;
 }
 
-// Sample k of a ray lies in the corner-index box [lo, hi].
-__device__ __forceinline__ bool in_block(const RayRec &R, int32_t k, const int32_t lo[3], const int32_t hi[3]) {
-    bool in = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int32_t c = fix_int(R.Q[a] + (int64_t)k * R.D[a]);
-        in = in && c >= lo[a] && c <= hi[a];
-    }
-    return in;
-}
-
 // The voxels of one block, staged through registers: rows of kBX + 1
 // elements from padded x index jx*kBX, as 16-byte chunks (the last chunk of
 // a row clamped to the row's end: its clamped voxels are never sampled).
@@ -209,14 +211,13 @@ struct BlockLoad {
     }
 };
 
-// Largest of the samples [kb, ke) of ray R in the LDS box of block lo.
+// Largest of the samples [kb, ke) of ray R in the LDS box of block lo;
+// sample kb is at position p.
 template <int FILTER, int BY, int BZ>
 __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int32_t kb, int32_t ke,
-                                           const int32_t lo[3], const float *box) {
+                                           const int64_t p[3], const int32_t lo[3], const float *box) {
     constexpr uint32_t bM = 4u * kPX, bS = 4u * kPX * (BY + 1);
-    int64_t q0 = R.Q[0] + (int64_t)kb * R.D[0];
-    int64_t q1 = R.Q[1] + (int64_t)kb * R.D[1];
-    int64_t q2 = R.Q[2] + (int64_t)kb * R.D[2];
+    int64_t q0 = p[0], q1 = p[1], q2 = p[2];
     const char *L = (const char *)box;
     float m = -INFINITY;
     for (int32_t k = kb; k < ke; ++k) {
@@ -244,12 +245,27 @@ __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int
     return m;
 }
 
-// The exact run [kb, ke) of samples of R in the corner-index box [lo, hi]:
-// per axis a float estimate of where the position crosses the box's faces,
-// widened, then trimmed from both ends by exact comparisons (the samples in a
-// box form one run, so trimming a run that contains them yields them).
+// The FP32 value of a 64-bit integer below 2^53 in magnitude, rounded once
+// (the same value as the plain conversion): both halves and their sum are
+// exact in FP64.
+__device__ __forceinline__ float i64_to_f32(int64_t v) {
+    return (float)fma((double)(int32_t)(v >> 32), 4294967296.0, (double)(uint32_t)v);
+}
+
+// The exact run [kb, ke) of samples of R in the corner-index box [lo, hi],
+// and the position p of sample kb: per axis a float estimate of where the
+// position crosses the box's faces, widened, then trimmed from both ends by
+// exact comparisons (the samples in a box form one run, so trimming a run
+// that contains them yields them).
+__device__ __forceinline__ bool in_box(int64_t x0, int64_t x1, int64_t x2, const int32_t lo[3],
+                                       const int32_t hi[3]) {
+    const int32_t c0 = fix_int(x0), c1 = fix_int(x1), c2 = fix_int(x2);
+    return ((uint32_t)(c0 >= lo[0]) & (uint32_t)(c0 <= hi[0]) & (uint32_t)(c1 >= lo[1]) & (uint32_t)(c1 <= hi[1]) &
+            (uint32_t)(c2 >= lo[2]) & (uint32_t)(c2 <= hi[2])) != 0;
+}
+
 __device__ __forceinline__ void block_run(const RayRec &R, const int32_t lo[3], const int32_t hi[3], int32_t &kb,
-                                          int32_t &ke) {
+                                          int32_t &ke, int64_t p[3]) {
     kb = 0;
     ke = R.n;
 #pragma unroll
@@ -259,15 +275,31 @@ __device__ __forceinline__ void block_run(const RayRec &R, const int32_t lo[3], 
         if (R.D[a] == 0) {
             if (lq > 0 || hq <= 0) ke = 0;
         } else {
-            const float ka = (float)lq * R.rd[a], kc = (float)hq * R.rd[a];
+            const float ka = i64_to_f32(lq) * R.rd[a], kc = i64_to_f32(hq) * R.rd[a];
             const float kmn = fminf(fmaxf(fminf(ka, kc), -1e9f), 1e9f);
             const float kmx = fminf(fmaxf(fmaxf(ka, kc), -1e9f), 1e9f);
             kb = max(kb, (int32_t)floorf(kmn) - 1);
             ke = min(ke, (int32_t)ceilf(kmx) + 2);
         }
     }
-    while (kb < ke && !in_block(R, kb, lo, hi)) ++kb;
-    while (ke > kb && !in_block(R, ke - 1, lo, hi)) --ke;
+    p[0] = R.Q[0] + (int64_t)kb * R.D[0];
+    p[1] = R.Q[1] + (int64_t)kb * R.D[1];
+    p[2] = R.Q[2] + (int64_t)kb * R.D[2];
+#pragma clang loop vectorize(disable) interleave(disable) unroll(disable)
+    while (kb < ke && !in_box(p[0], p[1], p[2], lo, hi)) {
+        ++kb;
+        p[0] += R.D[0]; p[1] += R.D[1]; p[2] += R.D[2];
+    }
+    if (kb < ke) {
+        int64_t e0 = R.Q[0] + (int64_t)(ke - 1) * R.D[0];
+        int64_t e1 = R.Q[1] + (int64_t)(ke - 1) * R.D[1];
+        int64_t e2 = R.Q[2] + (int64_t)(ke - 1) * R.D[2];
+#pragma clang loop vectorize(disable) interleave(disable) unroll(disable)
+        while (!in_box(e0, e1, e2, lo, hi)) {     // sample kb is inside: stops there at the latest
+            --ke;
+            e0 -= R.D[0]; e1 -= R.D[1]; e2 -= R.D[2];
+        }
+    }
 }
 
 // A workgroup walks blocks jx of its run along x (at most kMaxRun).  The
@@ -275,10 +307,9 @@ __device__ __forceinline__ void block_run(const RayRec &R, const int32_t lo[3], 
 // lane, into LDS.  The voxel loads of the next non-empty block are issued
 // before the current block is sampled, so their latency hides behind the
 // sampling.
-constexpr int kMaxRun = 64;
 
 template <typename S, int FILTER, int BY, int BZ, int NT>
-__global__ __launch_bounds__(NT) void k_mip_blocks(BlockArgs B) {
+__global__ __launch_bounds__(NT, (waves_per_simd<BY, BZ, NT>())) void k_mip_blocks(BlockArgs B) {
     using LD = BlockLoad<S, BY, BZ, NT>;
     __shared__ __align__(16) float box[LD::FLOATS + 8];
     __shared__ int4 rects[kMaxRun];
@@ -341,8 +372,9 @@ __global__ __launch_bounds__(NT) void k_mip_blocks(BlockArgs B) {
             const int64_t pix = pixel(rc, i);
             if (i != tid) R = B.tab[pix];
             int32_t kb, ke;
-            block_run(R, lo, hi, kb, ke);
-            if (kb < ke) atomicMax(out + pix, mip_enc(block_max<FILTER, BY, BZ>(V, R, kb, ke, lo, box)));
+            int64_t p[3];
+            block_run(R, lo, hi, kb, ke, p);
+            if (kb < ke) atomicMax(out + pix, mip_enc(block_max<FILTER, BY, BZ>(V, R, kb, ke, p, lo, box)));
         }
         R = Rn;
         t = tn;

@@ -232,9 +232,11 @@ static bool use_compact_path(const vr_ctx *ctx) {
 // MIP in object order (path 4) on one-brick layouts; it keeps per-pixel ray
 // records in the workspace.  The automatic choice (path 0 with the automatic
 // LDS budget) takes it for views whose far slab boxes, even in the best
-// orientation copy, would not fit the default 64 KiB budget (views oblique to
-// the axes): there the blocks read each voxel about once, while the
-// bundles' boxes overlap most.
+// orientation copy, exceed 50 KiB (views oblique to the axes): there the
+// blocks read each voxel about once, while the bundles' boxes overlap most.
+// The object-order frame costs about the same at every angle; the bundles'
+// frame grows with their box sizes, and 50 KiB is where the two cross on the
+// orbit views of an 8 GiB cube at 1920x1080.
 static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
     if (!ctx->vol.single || p->mode != VR_MIP || !ctx->has_camera) return false;
     if (ctx->tune.path == 4) return true;
@@ -246,7 +248,7 @@ static bool use_block_path(const vr_ctx *ctx, const vr_render_params *p) {
         best = std::min(best, vr_box_estimate_kib(ctx->camd, v, ctx->tune.packet_w,
                                                   ctx->tune.packet_h * ctx->tune.waves_per_group));
     }
-    return best > 64.0;
+    return best > 50.0;
 }
 
 // Automatic LDS budget of the slab path (tuning lds_kib = 0).  Two
@@ -597,10 +599,11 @@ int vr_render(vr_ctx *ctx, const vr_render_params *p, float *out_dev, void *ws, 
         if (ws && ws_bytes >= need) {
             MarchArgs b = a;
             b.vol = ctx->vol;                 // the x-fastest copy
-            // tuning for this path: lds_kib 8..63 takes 32x16x16 blocks (42 KiB of LDS), else 32x32x16
-            // (79 KiB); waves_per_group 8 runs 512 threads on the larger blocks; slab_max blocks per run
+            // tuning for this path: 32x16x16 blocks (42 KiB of LDS, three workgroups per CU) unless
+            // lds_kib is 64..144, which takes 32x32x16 (80 KiB, two per CU); waves_per_group 8 runs
+            // 512 threads on the larger blocks; slab_max blocks per run
             const vr_tuning &t = ctx->tune;
-            const int32_t shape = (t.lds_kib > 0 && t.lds_kib < 64) ? 0 : (t.waves_per_group >= 8 ? 2 : 1);
+            const int32_t shape = t.waves_per_group >= 8 ? 2 : (t.lds_kib >= 64 ? 1 : 0);
             const int32_t run = t.path == 4 ? t.slab_max : 8;
             return dev_check(ctx, launch_mip_blocks(b, p->filter, ws, run, shape, (hipStream_t)stream), "render");
         }

@@ -452,8 +452,8 @@ def test_object_order_mip_matches_marching(R, storage, orient):
             for filt in ("nearest", "trilinear"):
                 R.set_tuning(**{**base_t, "path": 1})
                 ref = R.render(mode="mip", filt=filt).cpu().numpy()
-                # block shapes 32x32x16 (256 and 512 threads) and 32x16x16; runs of 16, 1 and 3 blocks
-                for t in (dict(), dict(waves_per_group=8, slab_max=1), dict(lds_kib=32, slab_max=3)):
+                # block shapes 32x16x16, 32x32x16 with 512 threads and with 256; runs of 16, 1 and 3 blocks
+                for t in (dict(), dict(waves_per_group=8, slab_max=1), dict(lds_kib=96, slab_max=3)):
                     R.set_tuning(**{**base_t, "path": 4, **t})
                     out = torch.full(ref.shape, float("nan"), dtype=torch.float32, device="cuda")
                     img = R.render(mode="mip", filt=filt, out=out).cpu().numpy()
