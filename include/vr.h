@@ -153,7 +153,11 @@ typedef struct {
                                      image rows), 0/1/2 force the x/y/z-fastest copy */
     int32_t order;                /* tile order: 0 one contiguous band of tiles per XCD (L2 reuse),
                                      1 hardware order (work spread evenly over the XCDs),
-                                     2 4x4-tile blocks per XCD, blocks dealt over the XCDs in turn */
+                                     2 4x4-tile blocks per XCD, blocks dealt over the XCDs in turn,
+                                     3 (default) LDS-staged path: bundles in decreasing order of their
+                                     estimated box fetch, sorted on the device into the workspace
+                                     (vr_render_workspace_bytes); without that workspace, and on other
+                                     paths, as 1 */
 } vr_tuning;
 
 /* ---- context ---------------------------------------------------------- */
@@ -272,9 +276,12 @@ int vr_set_camera(vr_ctx *ctx, const vr_camera *cam);
  * save_for_backward (int32 per pixel, then from the next 256-byte boundary
  * ceil(max samples / VR_CHECKPOINT_INTERVAL) float planes of one value per
  * pixel); 64 bytes per pixel of ray records when the view is
- * rendered in object order (MIP, path 4 or the automatic choice); else 0.
- * With a smaller workspace an object-order view is rendered by the bundle
- * kernels instead (the same image). */
+ * rendered in object order (MIP, path 4 or the automatic choice); when it is
+ * rendered by the LDS-staged bundle kernel with tuning order 3, the bundle
+ * order: 4 bytes per bundle (from 256-byte boundaries) and 1 byte per bundle;
+ * else 0.  With a smaller workspace an object-order view is rendered by the
+ * bundle kernels instead, and bundles run in hardware order (the same
+ * image either way). */
 int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *params);
 
 /* Render the camera's viewport into out_dev: tile_h*tile_w*4 floats
@@ -286,8 +293,8 @@ int vr_render(vr_ctx *ctx, const vr_render_params *params, float *out_dev,
 /* vr_render for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation).
  * The only scratch a render needs without save_for_backward, the per-pixel
- * ray records of MIP in object order (vr_render_workspace_bytes), lives in a
- * fixed device array of vr_render_noalloc_max_bytes() = 128 MiB (ray records
+ * ray records of MIP in object order or the bundle order of the LDS-staged
+ * kernel (vr_render_workspace_bytes), lives in a fixed device array of vr_render_noalloc_max_bytes() = 128 MiB (ray records
  * of up to 2^21 pixels), one per GPU, held until the process ends; the call
  * allocates nothing.  The caller still passes the output.  Every call on one
  * GPU shares that GPU's array: calls that overlap in time on one GPU (two

@@ -73,7 +73,8 @@ struct Walker {
 __device__ __forceinline__ bool lane_pixel(const MarchArgs &A, int &px, int &py) {
     int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t gx, gy;
-    tile_xy(blockIdx.x, gridDim.x, A.groups_x, (int32_t)(gridDim.x / (uint32_t)A.groups_x), A.order, gx, gy);
+    tile_xy(blockIdx.x, gridDim.x, A.groups_x, (int32_t)(gridDim.x / (uint32_t)A.groups_x), A.order, A.tile_perm,
+            gx, gy);
     px = gx * A.packet_w + lane % A.packet_w;
     py = (gy * A.waves + wave) * A.packet_h + lane / A.packet_w;
     return px < A.cam.tile_w && py < A.cam.tile_h;

@@ -572,8 +572,8 @@ __global__ __launch_bounds__(512) void k_slab(SlabArgs SA) {
     __shared__ int32_t red[16];
     __shared__ double corners[24];
     int32_t gbx, gby;
-    tile_xy(blockIdx.x, gridDim.x, SA.m.groups_x, (int32_t)(gridDim.x / (uint32_t)SA.m.groups_x), SA.m.order, gbx,
-            gby);
+    tile_xy(blockIdx.x, gridDim.x, SA.m.groups_x, (int32_t)(gridDim.x / (uint32_t)SA.m.groups_x), SA.m.order,
+            SA.m.tile_perm, gbx, gby);
     slab_bundle<S, MODE, FILTER, ORI>(SA, gbx * SA.bw, gby * SA.bh, smem, red, corners);
 }
 
@@ -905,6 +905,117 @@ static hipError_t launch_slab_s(const SlabArgs &a, int32_t mode, int32_t filter,
     return launch_slab_t<S, VR_COMPOSITE, VR_TRILINEAR>(a, g, b, lds, s);
 }
 
+// ---- costliest bundles first --------------------------------------------
+// A CU starts the next workgroup when one finishes, in id order, so the frame
+// ends when the last-started bundles end.  Bundles differ in cost by up to
+// ~7x within one view (rays at 45 degrees between two axes make the widest
+// boxes), and a heavy one that starts late stretches the frame.  The bundles
+// are therefore launched in decreasing order of an estimate of the 128-byte
+// lines their boxes fetch: the boxes of two slabs 8 corner indices thick, at
+// a quarter and three quarters of the depth range the bundle's corner and
+// centre rays span along their dominant axis, each row counted at the mean
+// number of lines a row of its bytes touches from a random 4-byte offset,
+// times the range over 8.  The estimate orders the tiles only: every bundle
+// renders the same pixels in any order.
+
+// Estimated lines of the bundle with corner pixels (x0, y0), (x1, y1).
+__device__ double bundle_lines(const MarchArgs &A, int32_t x0, int32_t y0, int32_t x1, int32_t y1) {
+    const CamDev &c = A.cam;
+    const VolDev &v = A.vol;
+    const double N[3] = {(double)v.nx, (double)v.ny, (double)v.nz};
+    double o[4][3], d[4][3], dc[3] = {0.0, 0.0, 0.0};
+    double te[5], tx[5], ow[5][3], dw[5][3];
+    bool hit = false;
+    for (int k = 0; k < 5; ++k) {
+        const int32_t px = k < 4 ? ((k & 1) ? x1 : x0) : (x0 + x1) / 2;
+        const int32_t py = k < 4 ? ((k & 2) ? y1 : y0) : (y0 + y1) / 2;
+        Ray r{};
+        make_ray(c, v, c.tile_x0 + px, c.tile_y0 + py, A.step, r);
+        ow[k][0] = r.ox; ow[k][1] = r.oy; ow[k][2] = r.oz;
+        dw[k][0] = r.dx; dw[k][1] = r.dy; dw[k][2] = r.dz;
+        te[k] = r.t0;
+        tx[k] = r.n > 0 ? r.t1 : -1.0;
+        hit = hit || r.n > 0;
+        if (k < 4)
+            for (int a = 0; a < 3; ++a) { o[k][a] = ow[k][a]; d[k][a] = dw[k][a]; dc[a] += dw[k][a]; }
+    }
+    if (!hit) return 0.0;
+    int w = 0;
+    if (fabs(dc[1]) > fabs(dc[w])) w = 1;
+    if (fabs(dc[2]) > fabs(dc[w])) w = 2;
+    double lo = 1e300, hi = -1e300;
+    for (int k = 0; k < 5; ++k) {
+        if (tx[k] < 0.0) continue;
+        const double pa = ow[k][w] + te[k] * dw[k][w], pb = ow[k][w] + tx[k] * dw[k][w];
+        lo = fmin(lo, fmin(pa, pb));
+        hi = fmax(hi, fmax(pa, pb));
+    }
+    const int f = v.ori, m = (v.ori + 1) % 3, sl = (v.ori + 2) % 3;
+    const double es = v.dtype == VR_F32 ? 4.0 : 2.0;
+    double lines = 0.0;
+    for (int e = 0; e < 2; ++e) {
+        const double p0 = lo + (hi - lo) * (0.25 + 0.5 * e) - 4.0, p1 = p0 + 8.0;
+        double ext[3];
+        for (int a = 0; a < 3; ++a) {
+            if (a == w) { ext[a] = 9.0; continue; }
+            double mn = 1e300, mx = -1e300;
+            for (int k = 0; k < 4; ++k) {
+                // rays shallower than 0.2 along w are gathered directly by the
+                // bundle kernel; the clamp keeps their estimate finite and large
+                const double dwk = fabs(d[k][w]) < 0.2 ? copysign(0.2, d[k][w]) : d[k][w];
+                for (int q = 0; q < 2; ++q) {
+                    const double pw = q ? p1 : p0;
+                    const double x = o[k][a] + (pw - o[k][w]) / dwk * d[k][a];
+                    mn = fmin(mn, x);
+                    mx = fmax(mx, x);
+                }
+            }
+            ext[a] = fmin(fmax(floor(mx) - floor(mn) + 2.0, 2.0), N[a] + 2.0);
+        }
+        lines += ext[m] * ext[sl] * (floor((ext[f] * es + 124.0) / 128.0) + 1.0);
+    }
+    return lines * 0.5 * (hi - lo + 1.0) / 8.0;
+}
+
+// The estimate of every tile as a sort key: its logarithm in buckets 2^(1/8)
+// apart, costliest first (key 0).
+__global__ __launch_bounds__(256) void k_tile_cost(MarchArgs A, int32_t bw, int32_t bh, int32_t ntiles,
+                                                    uint8_t *key) {
+    const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= ntiles) return;
+    const int32_t tx = t % A.groups_x, ty = t / A.groups_x;
+    const int32_t x0 = tx * bw, y0 = ty * bh;
+    const int32_t x1 = min(x0 + bw, A.cam.tile_w) - 1, y1 = min(y0 + bh, A.cam.tile_h) - 1;
+    const double lines = bundle_lines(A, x0, y0, x1, y1);
+    key[t] = (uint8_t)(255 - (int32_t)fmin(log2(lines + 1.0) * 8.0, 255.0));
+}
+
+// One workgroup: a counting sort of the tiles by key in LDS, written as the
+// permutation (the order within a key is arbitrary).
+__global__ __launch_bounds__(1024) void k_tile_sort(int32_t ntiles, const uint8_t *key, int32_t *perm) {
+    __shared__ int32_t hist[256];
+    const int tid = threadIdx.x;
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    for (int32_t t = tid; t < ntiles; t += 1024) atomicAdd(&hist[key[t]], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int32_t h = hist[i];
+            hist[i] = run;
+            run += h;
+        }
+    }
+    __syncthreads();
+    for (int32_t t = tid; t < ntiles; t += 1024) perm[atomicAdd(&hist[key[t]], 1)] = t;
+}
+
+int64_t slab_order_bytes(int32_t w, int32_t h, int32_t bw, int32_t bh) {
+    const int64_t n = (int64_t)((w + bw - 1) / bw) * ((h + bh - 1) / bh);
+    return (n * 4 + 255) / 256 * 256 + n;
+}
+
 hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t bw, int32_t bh, int32_t cap_floats,
                        int32_t lmax, hipStream_t s) {
     SlabArgs a{};
@@ -919,6 +1030,16 @@ hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t
     a.m.groups_x = (m.cam.tile_w + bw - 1) / bw;
     int gy = (m.cam.tile_h + bh - 1) / bh;
     dim3 g((unsigned)(a.m.groups_x * gy)), b((unsigned)(bw * bh));
+    if (a.m.order == 3 && a.m.tile_perm && a.m.tile_key) {
+        const int32_t n = a.m.groups_x * gy;
+        hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.m, bw, bh, n,
+                           a.m.tile_key);
+        hipLaunchKernelGGL(k_tile_sort, dim3(1), dim3(1024), 0, s, n, (const uint8_t *)a.m.tile_key, a.m.tile_perm);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else {
+        a.m.tile_perm = nullptr;
+    }
     // box budget + one spare 8-float slot + the table (composite)
     size_t lds = (size_t)a.cap * 4 + 32 + (mode == VR_COMPOSITE ? (size_t)m.lut.n * 16 : 0);
     switch (m.vol.dtype) {

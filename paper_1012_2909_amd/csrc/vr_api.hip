@@ -315,14 +315,33 @@ int32_t vr_auto_box_kib(const CamDev &c, const VolDev &v, int32_t bw, int32_t bh
     return vr_box_estimate_kib(c, v, bw, bh) > 100.0 ? 144 : 64;
 }
 
-static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s) {
+// Workspace bytes of the costliest-first bundle order (tuning order 3 on
+// the LDS-staged path, without save_for_backward), else 0.
+static int64_t order_bytes(const vr_ctx *ctx, const vr_render_params *p) {
+    if (ctx->tune.order != 3 || p->save_for_backward || use_compact_path(ctx) || !use_slab_path(ctx, p)) return 0;
+    return slab_order_bytes(ctx->cam.tile_w, ctx->cam.tile_h, ctx->tune.packet_w,
+                            ctx->tune.packet_h * ctx->tune.waves_per_group);
+}
+
+// ws: the caller's workspace when it holds the bundle order (order_bytes),
+// else NULL (the bundles then run in hardware order).
+static hipError_t dispatch_render(vr_ctx *ctx, const MarchArgs &a, const vr_render_params *p, hipStream_t s,
+                                  void *ws = nullptr) {
     if (use_compact_path(ctx)) return launch_march_compact(a, p->mode, p->filter, ctx->tune.persistent_groups, s);
     if (use_slab_path(ctx, p)) {
-        const int32_t kib = ctx->tune.lds_kib > 0
-                                ? ctx->tune.lds_kib
-                                : vr_auto_box_kib(a.cam, a.vol, a.packet_w, a.packet_h * a.waves);
+        const int32_t bh = a.packet_h * a.waves;
+        const int32_t kib = ctx->tune.lds_kib > 0 ? ctx->tune.lds_kib
+                                                  : vr_auto_box_kib(a.cam, a.vol, a.packet_w, bh);
         int32_t cap = kib * 1024 / 4;
-        return launch_slab(a, p->mode, p->filter, a.packet_w, a.packet_h * a.waves, cap, ctx->tune.slab_max, s);
+        MarchArgs b = a;
+        b.tile_perm = nullptr;
+        b.tile_key = nullptr;
+        if (ws && a.order == 3) {
+            const int64_t n = (int64_t)((a.cam.tile_w + a.packet_w - 1) / a.packet_w) * ((a.cam.tile_h + bh - 1) / bh);
+            b.tile_perm = (int32_t *)ws;
+            b.tile_key = (uint8_t *)ws + (n * 4 + 255) / 256 * 256;
+        }
+        return launch_slab(b, p->mode, p->filter, a.packet_w, bh, cap, ctx->tune.slab_max, s);
     }
     if (ctx->tune.path == 0 && ctx->vol.single && p->mode == VR_COMPOSITE) {
         // the automatic shape of the direct kernel for early-stopping
@@ -572,7 +591,7 @@ int64_t vr_render_workspace_bytes(const vr_ctx *ctx, const vr_render_params *p) 
     if (check_params(const_cast<vr_ctx *>(ctx), p) != VR_OK) return VR_EINVAL;
     int64_t npix = (int64_t)ctx->cam.tile_w * ctx->cam.tile_h;
     if (use_block_path(ctx, p)) return mip_blocks_workspace(npix);
-    if (!p->save_for_backward) return 0;
+    if (!p->save_for_backward) return order_bytes(ctx, p);
     return align256(npix * 4) + ckpt_segs(ctx, p) * npix * 4;
 }
 
@@ -608,7 +627,9 @@ int vr_render(vr_ctx *ctx, const vr_render_params *p, float *out_dev, void *ws, 
             return dev_check(ctx, launch_mip_blocks(b, p->filter, ws, run, shape, (hipStream_t)stream), "render");
         }
     }
-    return dev_check(ctx, dispatch_render(ctx, a, p, (hipStream_t)stream), "render");
+    const int64_t ob = order_bytes(ctx, p);
+    void *ows = (ob > 0 && ws && ws_bytes >= ob) ? ws : nullptr;
+    return dev_check(ctx, dispatch_render(ctx, a, p, (hipStream_t)stream, ows), "render");
 }
 
 int vr_render_backward(vr_ctx *ctx, const vr_render_params *p, const float *grad_out, const void *ws,
@@ -691,7 +712,7 @@ static bool tuning_valid(const vr_tuning &t) {
     // persistent_groups, 1..32, as packets per wave)
     bool compact_shape = t.path != 3 || t.waves_per_group <= 4;
     bool copy = t.copy >= -1 && t.copy <= 2;
-    bool order = t.order >= 0 && t.order <= 2;
+    bool order = t.order >= 0 && t.order <= 3;
     return shape && waves && unroll && pg && path && lds && slab && slab_shape && compact_shape && copy && order;
 }
 

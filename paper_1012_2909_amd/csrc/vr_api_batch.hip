@@ -312,7 +312,7 @@ static std::vector<vr_tuning> candidates(const vr_ctx *ctx, bool batch) {
             for (int kib : {0, 48, 64, 96, 144})
                 for (int L : {8, 16, 32})
                     for (int pg : batch ? std::vector<int>{1, 2, 4} : std::vector<int>{4})
-                        c.push_back(vr_tuning{sh[0], sh[1], 4, 1, pg, 2, kib, L, -1, 1});
+                        c.push_back(vr_tuning{sh[0], sh[1], 4, 1, pg, 2, kib, L, -1, batch ? 1 : 3});
         }
     }
     return c;

@@ -339,10 +339,21 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nblocks) {
 //     of a view whose volume covers only part of the frame spreads evenly;
 //  2: blocks of 4 x 4 tiles, each run on one XCD, the blocks dealt over the
 //     XCDs in turn: neighbouring tiles share their XCD's L2 (overlapping
-//     voxel boxes are fetched once) and the work still spreads evenly.
-// Workgroups are dealt to the XCDs round-robin by id (bid mod 8).
+//     voxel boxes are fetched once) and the work still spreads evenly;
+//  3: the permutation perm (the LDS-staged path's bundles in decreasing
+//     order of their estimated box fetch), or order 1 when perm is NULL.
+// Workgroups are dealt to the XCDs round-robin by id (bid mod 8), and a
+// CU takes the next workgroup as one finishes: with the costliest tiles
+// first, the last workgroups to start are short ones.
 __device__ __forceinline__ void tile_xy(uint32_t bid, uint32_t nblocks, int32_t gx, int32_t gy, int order,
-                                        int32_t &tx, int32_t &ty) {
+                                        const int32_t *perm, int32_t &tx, int32_t &ty) {
+    if (order == 3) {
+        // the tile permutation of the ordering kernel (hardware order without one)
+        const uint32_t g = perm ? (uint32_t)perm[bid] : bid;
+        tx = (int32_t)(g % (uint32_t)gx);
+        ty = (int32_t)(g / (uint32_t)gx);
+        return;
+    }
     if (order == 2) {
         // enumeration E: strips of 4 tile rows, each walked column by column
         // (16 consecutive E indices form a 4 x 4 block, or a compact block

@@ -44,7 +44,7 @@ struct vr_ctx {
     vr_camera cam{};
     vr::CamDev camd{};
     // launch shape
-    vr_tuning tune{16, 4, 4, 2, 4, 0, 0, 16, -1, 1};
+    vr_tuning tune{16, 4, 4, 2, 4, 0, 0, 16, -1, 3};
     // pinned staging for small device tables, and the event of its last copy
     void *stage = nullptr;
     size_t stage_bytes = 0;

@@ -32,7 +32,13 @@ struct MarchArgs {
     int32_t groups_x;             // workgroups per tile row
     int32_t unroll;               // samples per inner iteration (direct path, one-brick layouts)
     int32_t order;                // tile order (see tile_xy)
+    int32_t *tile_perm;           // order 3, LDS-staged path: workgroup -> tile, costliest first; else NULL
+    uint8_t *tile_key;            // scratch of the ordering kernel: one byte per tile
 };
+
+// Bytes of caller workspace the costliest-first tile order of the LDS-staged
+// path needs for a viewport of w x h pixels in bundles of bw x bh.
+int64_t slab_order_bytes(int32_t w, int32_t h, int32_t bw, int32_t bh);
 
 // K0: transcode planes [z0, z1) of a float32 (z1-z0, ny, nx) source block
 // into the brick-major layout at vol.data.
@@ -64,7 +70,9 @@ int64_t mip_blocks_workspace(int64_t npix);
 hipError_t launch_mip_blocks(const MarchArgs &a, int32_t filter, void *ws, int32_t run, int32_t shape,
                              hipStream_t s);
 
-// K1/K2 with LDS-staged voxel boxes (single-brick layouts).
+// K1/K2 with LDS-staged voxel boxes (single-brick layouts).  With
+// m.order == 3 and m.tile_perm set, a first kernel orders the bundles by
+// their estimated box fetch.
 hipError_t launch_slab(const MarchArgs &m, int32_t mode, int32_t filter, int32_t bw, int32_t bh, int32_t cap_floats,
                        int32_t lmax, hipStream_t s);
 

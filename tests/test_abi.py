@@ -136,11 +136,11 @@ def test_argument_errors(hctx):
     assert L.vr_set_tuning(h, C.byref(t)) == vr.OK
     t2 = vr.Tuning()
     assert L.vr_get_tuning(h, C.byref(t2)) == vr.OK and (t2.packet_w, t2.waves_per_group) == (16, 2)
-    # LDS budget: 0 (automatic per view) or 8..144 KiB; tile orders 0..2
+    # LDS budget: 0 (automatic per view) or 8..144 KiB; tile orders 0..3
     for kib, ok in [(0, True), (8, True), (144, True), (4, False), (160, False), (-1, False)]:
         t = vr.Tuning(16, 4, 4, 1, 4, 2, kib, 16, -1, 1)
         assert (L.vr_set_tuning(h, C.byref(t)) == vr.OK) == ok, kib
-    for order, ok in [(0, True), (2, True), (3, False)]:
+    for order, ok in [(0, True), (2, True), (3, True), (4, False)]:
         t = vr.Tuning(16, 4, 4, 1, 4, 2, 64, 16, -1, order)
         assert (L.vr_set_tuning(h, C.byref(t)) == vr.OK) == ok, order
     # the LDS-staged path runs 4- or 8-wave groups only

@@ -135,7 +135,8 @@ TUNES = [dict(path=1), dict(path=1, packet_w=8, packet_h=8, waves_per_group=8),
          dict(path=1, copy=0), dict(path=1, copy=1), dict(path=1, copy=2, unroll=2),
          dict(path=2, copy=0), dict(path=2, copy=1), dict(path=2, copy=2, lds_kib=96),
          dict(path=2, copy=1, lds_kib=8, slab_max=2), dict(path=1, order=0), dict(path=2, order=0),
-         dict(path=1, order=1, unroll=4), dict(path=1, order=2), dict(path=2, order=2),
+         dict(path=1, order=1, unroll=4), dict(path=1, order=2), dict(path=2, order=2), dict(path=2, order=1),
+         dict(path=2, order=3, packet_w=64, packet_h=1), dict(path=2, order=3, packet_w=4, packet_h=16, lds_kib=32),
          dict(path=2, order=2, packet_w=32, packet_h=2, lds_kib=64), dict(path=1, order=2, packet_w=4, packet_h=16),
          dict(path=2, packet_w=32, packet_h=2, waves_per_group=8, lds_kib=128),
          dict(path=2, packet_w=16, packet_h=4, waves_per_group=8, lds_kib=16, order=2),
@@ -486,6 +487,41 @@ def test_object_order_workspace_and_fallback(R, cube64):
         assert vr.lib().vr_render(R.ctx, vr.C.byref(p), vr._ptr(out), None, 0, vr._stream()) == 0
         assert np.array_equal(out.cpu().numpy(), ref)
         assert np.array_equal(R.render(mode="mip").cpu().numpy(), ref)
+    finally:
+        R.set_tuning(**base_t)
+
+
+def test_bundle_order_workspace_and_fallback(R, cube64):
+    """Tile order 3 (the default) launches the LDS-staged bundles costliest
+    first from a permutation sorted on the device into the workspace (4 + 1
+    bytes per bundle); without the workspace the bundles run in hardware
+    order.  Every pixel is written once and the images are identical."""
+    from paper_1012_2909_amd import vr
+    lut = synth.lut_ramp()
+    base_t = R.get_tuning()
+    assert base_t["order"] == 3
+    try:
+        R.load_volume(torch.from_numpy(cube64))
+        R.set_lut(lut)
+        for w, h in ((97, 61), (300, 17), (1, 1)):
+            cam = synth.orbit_camera(cube64.shape, seed=5, w=w, h=h)
+            R.set_camera(cam)
+            for mode in ("mip", "composite"):
+                p = vr.params_struct(mode=mode, ert=1.0)
+                R.set_tuning(**{**base_t, "path": 2, "order": 1})
+                assert int(vr.lib().vr_render_workspace_bytes(R.ctx, vr.C.byref(p))) == 0
+                ref = R.render(mode=mode, ert=1.0).cpu().numpy()
+                R.set_tuning(**{**base_t, "path": 2, "order": 3})
+                n = ((w + 15) // 16) * ((h + 15) // 16)
+                need = int(vr.lib().vr_render_workspace_bytes(R.ctx, vr.C.byref(p)))
+                assert need == (n * 4 + 255) // 256 * 256 + n
+                shape = (h, w) if mode == "mip" else (h, w, 4)
+                for ws in (torch.empty(need, dtype=torch.uint8, device="cuda"), None):
+                    out = torch.full(shape, float("nan"), dtype=torch.float32, device="cuda")
+                    rc = vr.lib().vr_render(R.ctx, vr.C.byref(p), vr._ptr(out), vr._ptr(ws) if ws is not None else None,
+                                            need if ws is not None else 0, vr._stream())
+                    assert rc == 0
+                    assert np.array_equal(out.cpu().numpy(), ref), (w, h, mode, ws is None)
     finally:
         R.set_tuning(**base_t)
 
