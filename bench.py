@@ -214,13 +214,23 @@ def main():
     alg_bytes = {n: [b * 512 * esz + out_bytes[n] + (lut.table.nbytes if n == "composite" else 0)
                      for b in touched[n]] for n in modes}
 
+    # one workspace for every timed render (the object-order MIP's ray records,
+    # the bundle order), allocated before the timed region
+    ws_need = 1
+    for c in cams:
+        R.set_camera(c)
+        for name, kw in modes.items():
+            R.set_tuning(**tunes[name])
+            ws_need = max(ws_need, R.workspace_bytes(mode=kw["mode"], filt=kw["filt"], step=step, ert=kw["ert"]))
+    ws = torch.empty(ws_need, dtype=torch.uint8, device=dev)
+
     def run_step(k, evs=None):
         R.set_camera(cams[k % N_ANGLES])
         for name, kw in modes.items():
             R.set_tuning(**tunes[name])
             if evs is not None:
                 evs[name][0].record()
-            R.render(out=outs[name], **kw)
+            R.render(out=outs[name], workspace=ws, **kw)
             if evs is not None:
                 evs[name][1].record()
 

@@ -362,25 +362,50 @@ struct BoxWalk {
 // as the LDS budget allows at that depth (a perspective bundle widens with
 // distance), at most lmax.  The box loads of the next slab are issued before
 // the current slab is sampled, so their latency hides behind the sampling.
+// The plan of a slab is the same for every lane, so the first wave alone
+// computes it, one slab ahead, into two LDS slots (plans, reused from the
+// corner-ray scratch): slab i + 2 is planned while slab i is sampled, into the
+// slot of slab i, which every thread read before that iteration's first
+// barrier; the barriers of iteration i + 1 order the write before the reads.
 template <typename S, int MODE, int FILTER, int W, int ORI, int SW>
 __device__ __forceinline__ void run_slabs(const SlabArgs &SA, const Frustum &F, LaneState &ls, bool active,
                                           int32_t wlo, int32_t whi, float *box, const float4 *lut, int64_t pix,
-                                          int64_t npix) {
+                                          int64_t npix, SlabPlan *plans) {
     const MarchArgs &A = SA.m;
     const VolDev &V = A.vol;
     constexpr int AM = (ORI + 1) % 3, AS = (ORI + 2) % 3;   // middle and slowest axis
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const bool planner = tid < 64;
     // the position along W of the lane's last sample
     const int64_t qlast = ls.Q[W] + (int64_t)(ls.n > 0 ? ls.n - 1 : 0) * ls.D[W];
     auto remaining = [&](int32_t c) { return SW > 0 ? whi - c + 1 : c - wlo + 1; };
+    auto advance = [&](int32_t c, int32_t L) { return SW > 0 ? c + L : c - L; };
+    // the plan of the slab after the one starting at c with thickness L (none past the range)
+    auto plan_after = [&](int32_t c, int32_t L) {
+        SlabPlan p{};
+        const int32_t cn = advance(c, L);
+        if (remaining(cn) > 0) p = plan_slab<S, W, ORI, FILTER, SW>(SA, F, cn, L, remaining(cn), nthr);
+        return p;
+    };
     int32_t cur = SW > 0 ? wlo : whi;                 // first corner index not yet covered
+    __syncthreads();                                  // the plan slots may still hold the corner rays
+    if (planner) {
+        const SlabPlan p0 = plan_slab<S, W, ORI, FILTER, SW>(SA, F, cur, SA.lmax, remaining(cur), nthr);
+        const SlabPlan p1 = plan_after(cur, p0.L);
+        if (tid == 0) {
+            plans[0] = p0;
+            plans[1] = p1;
+        }
+    }
+    __syncthreads();
     uint4 raw[kMaxPasses];
     BoxWalk<S, ORI> wk;
-    SlabPlan nxt = plan_slab<S, W, ORI, FILTER, SW>(SA, F, cur, SA.lmax, remaining(cur), nthr);
+    SlabPlan nxt = plans[0];
     if (nxt.lds) {
         wk.init(nxt, V, box, tid, nthr);
         wk.load(raw, wk.row0);
     }
+    int32_t slot = 1;                                 // slot of the next slab's plan
     while (__syncthreads_or(active)) {
         if (remaining(cur) <= 0) break;
         const SlabPlan sl = nxt;
@@ -393,13 +418,19 @@ __device__ __forceinline__ void run_slabs(const SlabArgs &SA, const Frustum &F, 
             }
             __syncthreads();
         }
-        // plan the next slab and issue its loads
-        cur = SW > 0 ? cur + sl.L : cur - sl.L;
+        // the next slab's plan from its slot, and its loads; the first wave
+        // plans the slab after it into the other slot
+        cur = advance(cur, sl.L);
         if (remaining(cur) > 0) {
-            nxt = plan_slab<S, W, ORI, FILTER, SW>(SA, F, cur, sl.L, remaining(cur), nthr);
+            nxt = plans[slot];
             if (nxt.lds) {
                 wk.init(nxt, V, box, tid, nthr);
                 wk.load(raw, wk.row0);
+            }
+            slot ^= 1;
+            if (planner) {
+                const SlabPlan p2 = plan_after(cur, nxt.L);
+                if (tid == 0) plans[slot] = p2;
             }
         }
         if (active) {
@@ -533,14 +564,16 @@ __device__ __forceinline__ void slab_bundle(const SlabArgs &SA, int bx0, int by0
 
     if (wlo <= whi && bundle_ok) {
         const bool active = reg;
+        SlabPlan *plans = (SlabPlan *)corners;        // the corner rays have been read
+        static_assert(2 * sizeof(SlabPlan) <= 24 * sizeof(double), "two slab plans fit the corner-ray scratch");
         if (sw > 0) {
-            if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
-            else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
-            else run_slabs<S, MODE, FILTER, 2, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix, plans);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix, plans);
+            else run_slabs<S, MODE, FILTER, 2, ORI, 1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix, plans);
         } else {
-            if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
-            else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
-            else run_slabs<S, MODE, FILTER, 2, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix);
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix, plans);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix, plans);
+            else run_slabs<S, MODE, FILTER, 2, ORI, -1>(SA, F, ls, active, wlo, whi, box, lut, pix, npix, plans);
         }
     }
     // lanes outside the slab scheme (and any samples left over) march on
@@ -710,13 +743,13 @@ __global__ __launch_bounds__(256) void k_brick_slab(SlabArgs SA, const BrickJob 
     }
     if (wlo <= whi && bundle_ok) {
         if (sw > 0) {
-            if (w == 0) run_slabs<S, MODE, FILTER, 0, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
-            else if (w == 1) run_slabs<S, MODE, FILTER, 1, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
-            else run_slabs<S, MODE, FILTER, 2, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0, (SlabPlan *)corners);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0, (SlabPlan *)corners);
+            else run_slabs<S, MODE, FILTER, 2, 0, 1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0, (SlabPlan *)corners);
         } else {
-            if (w == 0) run_slabs<S, MODE, FILTER, 0, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
-            else if (w == 1) run_slabs<S, MODE, FILTER, 1, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
-            else run_slabs<S, MODE, FILTER, 2, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0);
+            if (w == 0) run_slabs<S, MODE, FILTER, 0, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0, (SlabPlan *)corners);
+            else if (w == 1) run_slabs<S, MODE, FILTER, 1, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0, (SlabPlan *)corners);
+            else run_slabs<S, MODE, FILTER, 2, 0, -1>(S2, F, ls, reg, wlo, whi, box, lut, 0, 0, (SlabPlan *)corners);
         }
     }
     // lanes outside the slab scheme (and any samples left over): direct gathers
