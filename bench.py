@@ -223,6 +223,15 @@ def main():
             R.set_tuning(**tunes[name])
             ws_need = max(ws_need, R.workspace_bytes(mode=kw["mode"], filt=kw["filt"], step=step, ert=kw["ert"]))
     ws = torch.empty(ws_need, dtype=torch.uint8, device=dev)
+    # one untimed render of every angle in every mode: the kernels of the timed
+    # steps are then loaded (a code object is loaded at its first launch, some
+    # milliseconds) whatever the warm-up count
+    for c in cams:
+        R.set_camera(c)
+        for name, kw in modes.items():
+            R.set_tuning(**tunes[name])
+            R.render(out=outs[name], workspace=ws, **kw)
+    torch.cuda.synchronize()
 
     def run_step(k, evs=None):
         R.set_camera(cams[k % N_ANGLES])

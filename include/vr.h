@@ -195,7 +195,12 @@ int64_t vr_debug_bounds_violations(vr_ctx *ctx);
  * fastest, each 256-byte aligned, so that every view direction finds a copy
  * whose rows run across its ray packets (shear-warp renderers keep such
  * principal-axis copies for the same reason); 1 stores the x-fastest copy
- * only.  Pure host function; returns < 0 on invalid sizes. */
+ * only.  An FP32 layout with three copies also stores a line copy for MIP in
+ * object order, from the next 128-element boundary: every padded row of the
+ * x-fastest copy as ceil((nx+2)/31) lines of 32 elements, line L holding the
+ * row's elements 31 L .. 31 L + 31 (the row's last element repeated past its
+ * end), (nz+2) * (ny+2) * lines * 32 elements.  Pure host function; returns
+ * < 0 on invalid sizes. */
 int64_t vr_volume_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t brick_edge,
                         int32_t orientations);
 

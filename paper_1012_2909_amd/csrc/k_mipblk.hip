@@ -13,7 +13,10 @@
 // Every sample lies in exactly one block.  A workgroup walks a run of blocks
 // along x; for each block it
 //   - copies the block's voxels (its corner indices and the +1 neighbours,
-//     (SX+1) x (SY+1) x (SZ+1)) from the padded x-fastest copy into LDS;
+//     (SX+1) x (SY+1) x (SZ+1)) into LDS: from the line copy of an FP32
+//     three-copy layout (SX = 31, one whole 128-byte line per row), else from
+//     the padded x-fastest copy (SX = 32: rows of 33 elements, which start and
+//     end inside lines);
 //   - bounds the block's pixels by projecting the corners of the part of the
 //     cube its samples can occupy (the hull's bounding rectangle with a small
 //     margin; the whole tile when the region comes within a voxel of the
@@ -42,7 +45,8 @@ struct RayRec {
 };
 static_assert(sizeof(RayRec) == 64, "ray record is one 64-byte line");
 
-constexpr int kBX = 32;                          // block edge along x (corner indices)
+constexpr int kBX = 32;                          // block edge along x (corner indices) on the x-fastest copy
+constexpr int kBXL = 31;                         // block edge along x on the line copy: one line per row
 constexpr int kPX = 36;                          // LDS row pitch (floats): kBX + 1 rounded up to 4
 constexpr int kMaxRun = 64;                      // blocks along x per workgroup
 
@@ -146,15 +150,18 @@ __device__ __forceinline__ void block_rect(const CamDev &c, const VolDev &v, con
     if (y1 < y0) y1 = y0;
 }
 
-// The voxels of one block, staged through registers: rows of kBX + 1
-// elements from padded x index jx*kBX, as 16-byte chunks (the last chunk of
-// a row clamped to the row's end: its clamped voxels are never sampled).
-// Loads and stores are branch-free (a chunk past the box reloads chunk 0 and
-// goes to a spare slot), so all loads of a block stay in flight together.
-template <typename S, int BY, int BZ, int NT>
+// The voxels of one block, staged through registers.  From the x-fastest
+// copy (LINES false): rows of kBX + 1 elements from padded x index jx*kBX, as
+// 16-byte chunks (the last chunk of a row clamped to the row's end: its
+// clamped voxels are never sampled).  From the line copy (LINES true, FP32):
+// one 32-element line per row, line jx of the row, which holds padded x
+// indices [31 jx, 31 jx + 31]: 8 chunks of one 128-byte line.  Loads and
+// stores are branch-free (a chunk past the box reloads chunk 0 and goes to a
+// spare slot), so all loads of a block stay in flight together.
+template <typename S, int BY, int BZ, int NT, bool LINES>
 struct BlockLoad {
     static constexpr int EPC = 16 / (int)sizeof(S);
-    static constexpr int CPR = (kBX + 1 + EPC - 1) / EPC;
+    static constexpr int CPR = LINES ? 32 / EPC : (kBX + 1 + EPC - 1) / EPC;
     static constexpr int ROWS = (BY + 1) * (BZ + 1);
     static constexpr int CHUNKS = CPR * ROWS;
     static constexpr int PASSES = (CHUNKS + NT - 1) / NT;
@@ -170,9 +177,14 @@ struct BlockLoad {
             const int cc = c < CHUNKS ? c : 0;
             const int row = cc / CPR, ch = cc - row * CPR;
             const int ly = row % (BY + 1), lz = row / (BY + 1);
-            const int64_t gx = min((int64_t)jx * kBX + ch * EPC, pmax_x);
             const int64_t gy = min(jy * BY + ly, py_max), gz = min(jz * BZ + lz, pz_max);
-            raw[p] = *(const uint4 *)((const S *)V.data + (gz * V.sz + gy * V.sy + gx));
+            if (LINES) {
+                const float *lines = (const float *)V.data + V.line_off;
+                raw[p] = *(const uint4 *)(lines + ((gz * V.Py + gy) * V.lpr + jx) * 32 + ch * EPC);
+            } else {
+                const int64_t gx = min((int64_t)jx * kBX + ch * EPC, pmax_x);
+                raw[p] = *(const uint4 *)((const S *)V.data + (gz * V.sz + gy * V.sy + gx));
+            }
         }
     }
     static __device__ __forceinline__ void store(const uint4 (&raw)[PASSES], float *box, int tid) {
@@ -213,7 +225,7 @@ struct BlockLoad {
 
 // Largest of the samples [kb, ke) of ray R in the LDS box of block lo;
 // sample kb is at position p.
-template <int FILTER, int BY, int BZ>
+template <int FILTER, int BX, int BY, int BZ>
 __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int32_t kb, int32_t ke,
                                            const int64_t p[3], const int32_t lo[3], const float *box) {
     constexpr uint32_t bM = 4u * kPX, bS = 4u * kPX * (BY + 1);
@@ -222,8 +234,8 @@ __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int
     float m = -INFINITY;
     for (int32_t k = kb; k < ke; ++k) {
         const int32_t ix = fix_int(q0) - lo[0], iy = fix_int(q1) - lo[1], iz = fix_int(q2) - lo[2];
-        // the box holds corner offsets [0, kBX] x [0, BY] x [0, BZ]: a sample's low corner is inside the block
-        VR_BOUNDS(V, ix >= 0 && iy >= 0 && iz >= 0 && ix < kBX && iy < BY && iz < BZ);
+        // the box holds corner offsets [0, BX] x [0, BY] x [0, BZ]: a sample's low corner is inside the block
+        VR_BOUNDS(V, ix >= 0 && iy >= 0 && iz >= 0 && ix < BX && iy < BY && iz < BZ);
         const uint32_t o = (uint32_t)(ix + __mul24(iy, kPX) + __mul24(iz, kPX * (BY + 1))) << 2;
         float s;
         if (FILTER == VR_NEAREST) {
@@ -308,9 +320,10 @@ __device__ __forceinline__ void block_run(const RayRec &R, const int32_t lo[3], 
 // before the current block is sampled, so their latency hides behind the
 // sampling.
 
-template <typename S, int FILTER, int BY, int BZ, int NT>
+template <typename S, int FILTER, int BY, int BZ, int NT, bool LINES>
 __global__ __launch_bounds__(NT, (waves_per_simd<BY, BZ, NT>())) void k_mip_blocks(BlockArgs B) {
-    using LD = BlockLoad<S, BY, BZ, NT>;
+    using LD = BlockLoad<S, BY, BZ, NT, LINES>;
+    constexpr int BX = LINES ? kBXL : kBX;
     __shared__ __align__(16) float box[LD::FLOATS + 8];
     __shared__ int4 rects[kMaxRun];
     const MarchArgs &A = B.m;
@@ -323,8 +336,8 @@ __global__ __launch_bounds__(NT, (waves_per_simd<BY, BZ, NT>())) void k_mip_bloc
     const int32_t lo_y = jy * BY - 1, lo_z = jz * BZ - 1;
     if (tid < nrun) {
         const int32_t j = j0 + tid;
-        const int32_t lo[3] = {j * kBX - 1, lo_y, lo_z};
-        const int32_t hi[3] = {lo[0] + kBX - 1, lo_y + BY - 1, lo_z + BZ - 1};
+        const int32_t lo[3] = {j * BX - 1, lo_y, lo_z};
+        const int32_t hi[3] = {lo[0] + BX - 1, lo_y + BY - 1, lo_z + BZ - 1};
         int32_t x0, x1, y0, y1;
         block_rect(A.cam, V, lo, hi, FILTER == VR_TRILINEAR ? 0.5 : 0.0, x0, x1, y0, y1);
         rects[tid] = make_int4(x0, x1, y0, y1);
@@ -365,8 +378,8 @@ __global__ __launch_bounds__(NT, (waves_per_simd<BY, BZ, NT>())) void k_mip_bloc
         asm volatile("" ::: "memory");
         if (tn < nrun) LD::load(raw, V, j0 + tn, jy, jz, tid);
         const int4 rc = rects[t];
-        const int32_t lo[3] = {(j0 + t) * kBX - 1, lo_y, lo_z};
-        const int32_t hi[3] = {lo[0] + kBX - 1, lo_y + BY - 1, lo_z + BZ - 1};
+        const int32_t lo[3] = {(j0 + t) * BX - 1, lo_y, lo_z};
+        const int32_t hi[3] = {lo[0] + BX - 1, lo_y + BY - 1, lo_z + BZ - 1};
         const int32_t npx = npix_of(rc);
         for (int32_t i = tid; i < npx; i += NT) {
             const int64_t pix = pixel(rc, i);
@@ -374,7 +387,7 @@ __global__ __launch_bounds__(NT, (waves_per_simd<BY, BZ, NT>())) void k_mip_bloc
             int32_t kb, ke;
             int64_t p[3];
             block_run(R, lo, hi, kb, ke, p);
-            if (kb < ke) atomicMax(out + pix, mip_enc(block_max<FILTER, BY, BZ>(V, R, kb, ke, p, lo, box)));
+            if (kb < ke) atomicMax(out + pix, mip_enc(block_max<FILTER, BX, BY, BZ>(V, R, kb, ke, p, lo, box)));
         }
         R = Rn;
         t = tn;
@@ -383,7 +396,13 @@ __global__ __launch_bounds__(NT, (waves_per_simd<BY, BZ, NT>())) void k_mip_bloc
 
 template <typename S, int FILTER, int BY, int BZ, int NT>
 static void launch_blocks_t(const BlockArgs &b, unsigned groups, hipStream_t s) {
-    hipLaunchKernelGGL((k_mip_blocks<S, FILTER, BY, BZ, NT>), dim3(groups), dim3(NT), 0, s, b);
+    if constexpr (__is_same(S, float)) {
+        if (b.m.vol.lpr > 0) {
+            hipLaunchKernelGGL((k_mip_blocks<S, FILTER, BY, BZ, NT, true>), dim3(groups), dim3(NT), 0, s, b);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_mip_blocks<S, FILTER, BY, BZ, NT, false>), dim3(groups), dim3(NT), 0, s, b);
 }
 
 template <int BY, int BZ, int NT>
@@ -418,7 +437,8 @@ hipError_t launch_mip_blocks(const MarchArgs &a, int32_t filter, void *ws, int32
     b.m = a;
     b.tab = tab;
     // blocks cover corner indices [-1, N] of each axis
-    b.nb[0] = (v.nx + 2 + kBX - 1) / kBX;
+    // the line copy, when the layout holds one (FP32 with three copies), else the x-fastest copy
+    b.nb[0] = (v.lpr > 0 && v.dtype == VR_F32) ? v.lpr : (v.nx + 2 + kBX - 1) / kBX;
     b.nb[1] = (v.ny + 2 + by - 1) / by;
     b.nb[2] = (v.nz + 2 + bz - 1) / bz;
     b.run = run;

@@ -156,6 +156,28 @@ static hipError_t launch_copies(const float *src, const VolDev &v, int64_t z0, i
     return hipSuccess;
 }
 
+// The line copy (FP32 three-copy layouts): padded row (lz, ly) cut into
+// lines of 32 elements, element e of line L = padded x index 31 L + e,
+// clamped to the row's last index.  One thread per element; blockIdx.y is the
+// padded row within the plane, blockIdx.z the padded plane from lz0.  Only
+// planes whose source plane lies in [z0, z1) are written.
+__global__ __launch_bounds__(256) void k_transcode_lines(const float *__restrict__ src, VolDev v,
+                                                         float *__restrict__ dst, int32_t z0, int32_t z1,
+                                                         int32_t ly0, int32_t lz0) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row_elems = (int64_t)v.lpr * 32;
+    if (e >= row_elems) return;
+    const int32_t ly = ly0 + (int32_t)blockIdx.y, lz = lz0 + (int32_t)blockIdx.z;
+    const int32_t nx = v.nx, ny = v.ny, nz = v.nz;
+    auto clampi = [](int64_t i, int32_t hi) { return (int32_t)(i < 0 ? 0 : (i > hi ? hi : i)); };
+    const int32_t gz = clampi(lz - 1, nz - 1);
+    if (gz < z0 || gz >= z1) return;
+    const int32_t gy = clampi(ly - 1, ny - 1);
+    const int64_t L = e >> 5, px = 31 * L + (e & 31);                 // padded x index
+    const int32_t gx = clampi(min(px, (int64_t)nx + 1) - 1, nx - 1);
+    dst[((int64_t)lz * v.Py + ly) * row_elems + e] = src[((int64_t)(gz - z0) * ny + gy) * nx + gx];
+}
+
 hipError_t launch_transcode(const float *src, const VolDev &v, int64_t z0, int64_t z1, hipStream_t s) {
     // brick z-layers whose stored planes (with apron) touch [z0, z1)
     int64_t bz_lo = (z0 - 1) >= 0 ? (z0 - 1) / v.Bz : 0;
@@ -180,11 +202,29 @@ hipError_t launch_transcode(const float *src, const VolDev &v, int64_t z0, int64
             if (e != hipSuccess) return e;
         }
     if (v.orients < 3) return hipSuccess;
+    hipError_t e;
     switch (v.dtype) {
-        case VR_F32: return launch_copies<float>(src, v, z0, z1, s);
-        case VR_F16: return launch_copies<_Float16>(src, v, z0, z1, s);
-        default: return launch_copies<bf16_t>(src, v, z0, z1, s);
+        case VR_F32: e = launch_copies<float>(src, v, z0, z1, s); break;
+        case VR_F16: e = launch_copies<_Float16>(src, v, z0, z1, s); break;
+        default: e = launch_copies<bf16_t>(src, v, z0, z1, s); break;
     }
+    if (e != hipSuccess || v.lpr <= 0 || v.dtype != VR_F32) return e;
+    // padded planes whose source plane lies in [z0, z1): z + 1 for z in the
+    // slab, plus the apron planes 0 and nz + 1 with the first and last slab
+    const int64_t lz_lo = z0 == 0 ? 0 : z0 + 1, lz_hi = z1 == v.nz ? (int64_t)v.nz + 1 : z1;
+    float *dst = (float *)v.data + v.line_off;
+    const unsigned gxb = (unsigned)(((int64_t)v.lpr * 32 + 255) / 256);
+    for (int64_t lz = lz_lo; lz <= lz_hi; lz += 65535)
+        for (int64_t ly = 0; ly < v.Py; ly += 65535) {
+            dim3 g(gxb, (unsigned)(v.Py - ly < 65535 ? v.Py - ly : 65535),
+                   (unsigned)(lz_hi + 1 - lz < 65535 ? lz_hi + 1 - lz : 65535)),
+                b(256);
+            hipLaunchKernelGGL(k_transcode_lines, g, b, 0, s, src, v, dst, (int32_t)z0, (int32_t)z1, (int32_t)ly,
+                               (int32_t)lz);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 
 }  // namespace vr

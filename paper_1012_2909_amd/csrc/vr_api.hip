@@ -464,6 +464,11 @@ bool vr_layout_of(int64_t nx, int64_t ny, int64_t nz, int32_t storage, int32_t B
         copy_pitches(d, c, pf, pm, ps);
         total = d.copy_off[c] + pf * pm * ps;
     }
+    if (orients == 3 && storage == VR_F32) {
+        d.lpr = (int32_t)((nx + 2 + 30) / 31);
+        d.line_off = (total + 127) / 128 * 128;
+        total = d.line_off + (int64_t)d.Pz * d.Py * d.lpr * 32;
+    }
     if (v) *v = d;
     if (bytes) *bytes = total * esize(storage);
     return true;

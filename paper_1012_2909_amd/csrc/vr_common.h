@@ -34,6 +34,13 @@ struct CamDev {
 // ray packets, so neighbouring lanes share cache lines whatever the view.
 // data/sx/sy/sz/ori describe the copy a kernel reads; brick layouts have
 // one copy, x fastest (sx = 1, sy = Px, sz = Px*Py).
+//
+// An FP32 three-copy layout also holds a line copy for the object-order MIP:
+// each padded row of the x-fastest copy cut into lines of 32 elements, line
+// L holding padded x indices [31 L, 31 L + 31] (the last index repeated past
+// the row's end), lines of a row consecutive, rows in (z, y) order.  A line is
+// one 128-byte cache line, and 31 corner indices with their +1 neighbour fit
+// in one line, so a block of 31 corner indices along x reads whole lines.
 struct VolDev {
     const void *data;     // element 0 of the copy (or brick array) in use
     int32_t nx, ny, nz;
@@ -48,6 +55,9 @@ struct VolDev {
     int32_t orients;      // copies stored (1 or 3)
     int32_t pad;
     int64_t copy_off[3];  // element offset of each copy from the layout base
+    int64_t line_off;     // element offset of the line copy (FP32 three-copy layouts), else 0
+    int32_t lpr;          // lines per padded row of the line copy, 0 when there is none
+    int32_t pad2;
     uint32_t *dbg;        // debug builds: device counter of index-range violations (else NULL)
 };
 

@@ -65,7 +65,10 @@ def test_volume_bytes_is_pure_and_matches_layout():
     c1 = r8(48) * 40 * 66
     c2 = r8(38) * 66 * 50
     a = lambda e: (e + 127) // 128 * 128
-    assert L.vr_volume_bytes(64, 48, 38, 0, 0, 3) == (a(c0) + a(c1) + c2) * 4
+    # FP32 with three copies adds the line copy: 31-element steps along x in 32-element lines
+    lines = 40 * 50 * ((64 + 2 + 30) // 31) * 32
+    assert L.vr_volume_bytes(64, 48, 38, 0, 0, 3) == (a(a(c0) + a(c1) + c2) + lines) * 4
+    assert L.vr_volume_bytes(64, 48, 38, 1, 0, 3) == (a(c0) + a(c1) + c2) * 2
     assert L.vr_volume_bytes(64, 48, 38, 0, 16, 3) < 0        # copies need one brick
     assert L.vr_volume_bytes(64, 48, 38, 0, 0, 2) < 0
 
