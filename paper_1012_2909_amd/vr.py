@@ -249,7 +249,8 @@ class Renderer:
     def load_volume(self, vol, storage="f32", brick=0, orientations=None):
         """vol: float32 (nz, ny, nx) cuda tensor (or numpy array, uploaded).
         orientations: 3 keeps x-, y- and z-fastest copies (one-brick layouts;
-        the default there), 1 the x-fastest copy only."""
+        the default there; with FP32 storage also the line copy the
+        object-order MIP reads), 1 the x-fastest copy only."""
         if not torch.is_tensor(vol):
             vol = torch.from_numpy(vol)
         vol = vol.to(self.device, torch.float32).contiguous()
