@@ -526,6 +526,46 @@ def test_bundle_order_workspace_and_fallback(R, cube64):
         R.set_tuning(**base_t)
 
 
+def test_line_copy_layout(R):
+    """The layout of an FP32 cube with three copies, read back from HBM: copy 0
+    is the padded x-fastest cube (clamp-to-edge apron, rows padded to 8
+    elements), copies 1 and 2 the same cube y- and z-fastest, and the line copy after the third copy holds every padded row
+    as ceil((nx+2)/31) lines of 32 elements, line L = the row's elements
+    31 L .. 31 L + 31, the row's last element past its end (the layout
+    include/vr.h states for vr_volume_bytes)."""
+    nz, ny, nx = 5, 7, 70
+    rng = np.random.default_rng(41)
+    vol = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    store = R.load_volume(torch.from_numpy(vol), storage="f32", orientations=3)
+    torch.cuda.synchronize()
+    mem = store.cpu().numpy().view(np.float32)
+    r8 = lambda n: (n + 2 + 7) // 8 * 8
+    a128 = lambda e: (e + 127) // 128 * 128
+    px = r8(nx)
+    c0 = px * (ny + 2) * (nz + 2)
+    c1 = r8(ny) * (nz + 2) * (nx + 2)
+    c2 = r8(nz) * (nx + 2) * (ny + 2)
+    line_off = a128(a128(c0) + a128(c1) + c2)
+    lpr = (nx + 2 + 30) // 31
+    assert mem.size == line_off + (nz + 2) * (ny + 2) * lpr * 32
+    zi = np.clip(np.arange(nz + 2) - 1, 0, nz - 1)
+    yi = np.clip(np.arange(ny + 2) - 1, 0, ny - 1)
+    xi = np.clip(np.arange(px) - 1, 0, nx - 1)
+    padded = vol[zi][:, yi][:, :, xi]
+    assert np.array_equal(mem[:c0].reshape(nz + 2, ny + 2, px), padded)
+    full = padded[:, :, :nx + 2]                 # (z, y, x) over padded indices 0 .. n+1
+    o1 = a128(c0)
+    o2 = o1 + a128(c1)
+    copy1 = mem[o1:o1 + c1].reshape(nx + 2, nz + 2, r8(ny))[:, :, :ny + 2]   # (x, z, y), y fastest
+    assert np.array_equal(copy1, full.transpose(2, 0, 1))
+    copy2 = mem[o2:o2 + c2].reshape(ny + 2, nx + 2, r8(nz))[:, :, :nz + 2]   # (y, x, z), z fastest
+    assert np.array_equal(copy2, full.transpose(1, 2, 0))
+    idx = np.minimum(31 * np.arange(lpr)[:, None] + np.arange(32)[None, :], nx + 1)
+    want = padded[:, :, idx]                     # (nz+2, ny+2, lpr, 32)
+    got = mem[line_off:].reshape(nz + 2, ny + 2, lpr, 32)
+    assert np.array_equal(got, want)
+
+
 def test_layout_grids_past_65535_planes(R):
     """A cube of 70000 planes along z: K0 writes copy 0 and the transposed
     copies in launches of at most 65535 planes each (a grid dimension's
