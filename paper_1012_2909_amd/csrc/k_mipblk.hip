@@ -229,11 +229,17 @@ template <int FILTER, int BX, int BY, int BZ>
 __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int32_t kb, int32_t ke,
                                            const int64_t p[3], const int32_t lo[3], const float *box) {
     constexpr uint32_t bM = 4u * kPX, bS = 4u * kPX * (BY + 1);
-    int64_t q0 = p[0], q1 = p[1], q2 = p[2];
+    // positions relative to the block's low corner: the integer part is then
+    // the box index, the fraction is unchanged
+    int64_t q0 = p[0] - (int64_t)lo[0] * 4294967296LL, q1 = p[1] - (int64_t)lo[1] * 4294967296LL;
+    int64_t q2 = p[2] - (int64_t)lo[2] * 4294967296LL;
+    // opaque to the optimizer, which would otherwise keep p as the loop's
+    // positions and subtract the corner again at every sample
+    asm volatile("" : "+v"(q0), "+v"(q1), "+v"(q2));
     const char *L = (const char *)box;
     float m = -INFINITY;
     for (int32_t k = kb; k < ke; ++k) {
-        const int32_t ix = fix_int(q0) - lo[0], iy = fix_int(q1) - lo[1], iz = fix_int(q2) - lo[2];
+        const int32_t ix = fix_int(q0), iy = fix_int(q1), iz = fix_int(q2);
         // the box holds corner offsets [0, BX] x [0, BY] x [0, BZ]: a sample's low corner is inside the block
         VR_BOUNDS(V, ix >= 0 && iy >= 0 && iz >= 0 && ix < BX && iy < BY && iz < BZ);
         const uint32_t o = (uint32_t)(ix + __mul24(iy, kPX) + __mul24(iz, kPX * (BY + 1))) << 2;
@@ -242,8 +248,13 @@ __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int
             s = *(const float *)(L + o);
         } else {
             const float fx = fix_frac(q0), fy = fix_frac(q1), fz = fix_frac(q2);
+            // one opaque base register for the far plane, so that its four
+            // reads pair into two two-element LDS reads off it (the plane's
+            // offset exceeds their immediate range)
+            uint32_t oz = o + bS;
+            asm volatile("" : "+v"(oz));
             const float *pa = (const float *)(L + o), *pb = (const float *)(L + o + bM);
-            const float *pc = (const float *)(L + o + bS), *pd = (const float *)(L + o + bM + bS);
+            const float *pc = (const float *)(L + oz), *pd = (const float *)(L + oz + bM);
             const float c000 = pa[0], c100 = pa[1], c010 = pb[0], c110 = pb[1];
             const float c001 = pc[0], c101 = pc[1], c011 = pd[0], c111 = pd[1];
             const float x00 = fmaf(fx, c100 - c000, c000), x10 = fmaf(fx, c110 - c010, c010);
