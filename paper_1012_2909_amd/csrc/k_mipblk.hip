@@ -262,7 +262,12 @@ __device__ __forceinline__ float block_max(const VolDev &V, const RayRec &R, int
             const float y0 = fmaf(fy, x10 - x00, x00), y1 = fmaf(fy, x11 - x01, x01);
             s = fmaf(fz, y1 - y0, y0);
         }
-        m = fmaxf(m, s);
+        // max(m, s) as the bare instruction: both are results of FP
+        // arithmetic (or -inf), so the quieting the compiler would add for
+        // fmaxf is not needed
+        float r;
+        asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(s), "v"(m));
+        m = r;
         q0 += R.D[0]; q1 += R.D[1]; q2 += R.D[2];
     }
     return m;
